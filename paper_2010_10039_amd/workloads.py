@@ -1,0 +1,142 @@
+"""Seeded synthetic symbol streams shaped like the paper's workloads.
+
+The paper evaluates on byte text (enwik8/9, Silesia), on SZ quantization
+codes of a cosmology field (Nyx-Quant: 1024 symbols, 2-byte codes) and on
+k-mer codes (Sec. 5.1.3).  None of those files is available, so these
+generators stand in for them with the same value types, alphabet sizes and
+kind of distribution.  Every generator is a pure function of its arguments
+and seed.  The GPU path and the CPU oracle both consume the bytes these
+functions return; nothing here performs any part of the Huffman method.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def gaussian_codes(n: int = 1 << 20, alphabet: int = 1024, mean: float = 512.0,
+                   sigma: float = 2.0, seed: int = 0, dtype=np.uint16) -> np.ndarray:
+    """i.i.d. discrete Gaussian: clip(rint(N(mean, sigma)), 0, alphabet-1)."""
+    rng = np.random.default_rng(seed)
+    v = np.rint(rng.normal(mean, sigma, size=n))
+    return np.clip(v, 0, alphabet - 1).astype(dtype)
+
+
+def zipf_bytes(n: int = 100_000_000, s: float = 1.1, alphabet: int = 256, seed: int = 0,
+               dtype=np.uint8) -> np.ndarray:
+    """Zipf(s) over a random permutation of the symbol ids (text-like bytes).
+
+    p_k is proportional to k^-s for ranks k = 1..alphabet; rank k is mapped to
+    symbol perm[k-1]."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(alphabet)
+    p = np.arange(1, alphabet + 1, dtype=np.float64) ** (-s)
+    p /= p.sum()
+    out = np.empty(n, dtype=dtype)
+    step = 1 << 24
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        out[lo:hi] = perm[rng.choice(alphabet, size=hi - lo, p=p)].astype(dtype)
+    return out
+
+
+def _smooth_field(dim: int, rng: np.random.Generator, nwaves: int = 8):
+    """Sum of `nwaves` random 3D sinusoids on a dim^3 grid, in float64.
+
+    f[i,j,k] = sum_q a_q sin(2 pi (u_q i + v_q j + w_q k) / dim + phi_q), with
+    a ~ U(0.5, 1.5), (u, v, w) ~ U{1..8}^3, phi ~ U[0, 2 pi).  The angle is
+    split as (u i + v j)/dim + phi and w k/dim, and sin(A + B) is expanded, so
+    only dim^2 + dim transcendental evaluations are needed."""
+    import torch
+
+    a = rng.uniform(0.5, 1.5, nwaves)
+    uvw = rng.integers(1, 9, size=(nwaves, 3))
+    phi = rng.uniform(0.0, 2.0 * math.pi, nwaves)
+    idx = np.arange(dim, dtype=np.float64)
+    f = torch.zeros((dim, dim, dim), dtype=torch.float64)
+    for q in range(nwaves):
+        ang_ij = 2.0 * math.pi * (uvw[q, 0] * idx[:, None] + uvw[q, 1] * idx[None, :]) / dim + phi[q]
+        ang_k = 2.0 * math.pi * uvw[q, 2] * idx / dim
+        s_ij = torch.from_numpy(np.sin(ang_ij))[:, :, None]
+        c_ij = torch.from_numpy(np.cos(ang_ij))[:, :, None]
+        s_k = torch.from_numpy(np.sin(ang_k))[None, None, :]
+        c_k = torch.from_numpy(np.cos(ang_k))[None, None, :]
+        f.addcmul_(s_ij, c_k, value=float(a[q]))
+        f.addcmul_(c_ij, s_k, value=float(a[q]))
+    return f
+
+
+def lorenzo_quant_codes(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01,
+                        eb_rel: float = 1e-4, radius: int = 512) -> np.ndarray:
+    """Error-bounded quantization codes of a smooth 3D field (SZ-style).
+
+    The stand-in for the paper's Nyx-Quant input (Sec. 5.1.3): a dim^3 float32
+    field made of 8 random sinusoids plus Gaussian noise of standard deviation
+    noise_rel_std * std(field); absolute error bound eb = eb_rel * value range.
+    Each value is prequantized to d = rint(x / (2 eb)); the 3D Lorenzo
+    predictor's residual (the mixed first difference along i, j, k with zero
+    padding outside the grid) is offset by `radius`; codes outside
+    [1, 2*radius - 1] become 0, SZ's outlier marker.  Returns uint16 codes in
+    C order, alphabet 2*radius."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    f = _smooth_field(dim, rng)
+    sd = float(f.std())
+    x = f.to(torch.float32)
+    del f
+    g = torch.Generator().manual_seed(int(rng.integers(0, 2**62)))
+    noise = torch.randn(x.shape, generator=g, dtype=torch.float32)
+    x.add_(noise, alpha=noise_rel_std * sd)
+    del noise
+    eb = eb_rel * float(x.max() - x.min())
+    d = torch.round(x.to(torch.float64) / (2.0 * eb)).to(torch.int32)
+    del x
+    for axis in range(3):
+        e = d.clone()
+        sl_hi = [slice(None)] * 3
+        sl_lo = [slice(None)] * 3
+        sl_hi[axis] = slice(1, None)
+        sl_lo[axis] = slice(None, -1)
+        e[tuple(sl_hi)] -= d[tuple(sl_lo)]
+        d = e
+    q = d.add_(radius)
+    q[(q < 1) | (q > 2 * radius - 1)] = 0
+    return q.reshape(-1).to(torch.int32).numpy().astype(np.uint16)
+
+
+def skewed_histogram(alphabet: int, total: int, seed: int = 0, kind: str = "normal") -> np.ndarray:
+    """A histogram (not a stream) for codebook-only workloads with large
+    alphabets (the paper's synthetic normally distributed histograms, Sec. 5.2.1).
+
+    kind = "normal": counts of `total` draws from N(alphabet/2, alphabet/8)
+    clipped to the alphabet; "uniform": total spread evenly."""
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        h = np.full(alphabet, total // alphabet, dtype=np.uint64)
+        h[: total % alphabet] += 1
+        return h.astype(np.uint32)
+    v = np.clip(np.rint(rng.normal(alphabet / 2, alphabet / 8, size=total)), 0, alphabet - 1)
+    return np.bincount(v.astype(np.int64), minlength=alphabet).astype(np.uint32)
+
+
+WORKLOADS = {
+    "gaussian_1M_u16_A1024": dict(kind="gaussian", n=1 << 20, alphabet=1024, chunk=4096),
+    "lorenzo3d_512cube_u16_A1024": dict(kind="lorenzo", dim=512, alphabet=1024, chunk=4096),
+    "zipf_100M_u8_A256": dict(kind="zipf", n=100_000_000, alphabet=256, chunk=4096),
+}
+
+
+def make(name: str, scale: int = 0) -> np.ndarray:
+    """Generate a named workload.  `scale` > 0 shrinks it for quick tests:
+    n is divided by 2**scale (the Lorenzo grid edge by 2**(scale/3) rounded)."""
+    w = WORKLOADS[name]
+    if w["kind"] == "gaussian":
+        return gaussian_codes(n=max(1, w["n"] >> scale), alphabet=w["alphabet"], seed=0)
+    if w["kind"] == "zipf":
+        return zipf_bytes(n=max(1, w["n"] >> scale), alphabet=w["alphabet"], seed=0)
+    if w["kind"] == "lorenzo":
+        dim = max(8, int(round(w["dim"] / 2 ** (scale / 3))))
+        return lorenzo_quant_codes(dim=dim, seed=0)
+    raise KeyError(name)
