@@ -1,0 +1,173 @@
+/*
+ * hf.h -- C ABI of libhf, an MI355X (gfx950) Huffman encoder for streams of
+ * fixed-width integer symbols, after Tian et al., "Revisiting Huffman Coding:
+ * Toward Extreme Performance on Modern GPU Architectures" (arXiv 2010.10039).
+ *
+ * The paper splits encoding into four stages (Sec. 4): histogramming,
+ * codebook construction, canonization, and encoding with bit
+ * concatenation.  hf_histogram is stage 1, hf_build_codebook is stages 2+3,
+ * hf_encode is stage 4; hf_decode_check re-reads the stream with the
+ * canonical decode tables and compares it with the input.
+ *
+ * Conventions shared by every entry point:
+ *  - Every buffer argument named d_* is DEVICE memory owned by the caller.
+ *    libhf never allocates, frees or retains device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work on that stream; they return before it runs.
+ *  - The return value reports errors the host can detect (arguments,
+ *    workspace size, launch failure).  Errors found while kernels run are
+ *    written to *d_status (one uint32, caller-zeroed) with first-error-wins
+ *    semantics; the caller reads it after synchronizing.
+ *  - A workspace (d_ws, ws_bytes) is scratch device memory, at least
+ *    hf_workspace_bytes() bytes, 256-byte aligned, with no required
+ *    contents.  One workspace must not be used by two calls that can run at
+ *    the same time.
+ *  - Symbols are uint8 (sym_bytes = 1) or little-endian uint16
+ *    (sym_bytes = 2); 1 <= alphabet <= 65536, alphabet <= 256 for uint8;
+ *    n < 2^32 symbols per call.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HF_OK = 0,
+  HF_ERR_ARG = 1,        /* bad argument (host) */
+  HF_ERR_WORKSPACE = 2,  /* workspace missing or too small (host) */
+  HF_ERR_LAUNCH = 3,     /* a kernel launch failed (host) */
+  HF_ERR_SYMBOL = 16,    /* a symbol >= alphabet, or one without a code (device) */
+  HF_ERR_CAPACITY = 17,  /* encoded stream longer than the output buffer (device) */
+  HF_ERR_CODELEN = 18,   /* a code longer than 64 bits (device; unreachable for n < 2^32) */
+  HF_ERR_MISMATCH = 19,  /* hf_decode_check found a difference (device) */
+  HF_ERR_INTERNAL = 20   /* a bounded wait or loop hit its limit (device; a bug guard) */
+} hf_status;
+
+#define HF_MAX_CODELEN 64
+
+/*
+ * The codebook: all pointers are device arrays owned by the caller.
+ *   cl[alphabet]  uint8   code length of each symbol; 0 = symbol unused.
+ *   cw[alphabet]  uint64  codeword in the low cl bits, sent MSB first; 0 if unused.
+ *   first[65]     uint64  first (smallest) codeword of each length l in
+ *                         [1, Lmax]; 0 for l = 0 and l > Lmax.
+ *   entry[65]     uint32  number of codewords shorter than l, l in [0, 64].
+ *   rev[alphabet] uint32  symbols ordered by (length, symbol); rev[entry[l] + j]
+ *                         holds codeword first[l] + j.  Entries [m, alphabet)
+ *                         are left untouched.
+ *   info[4]       uint64  {m = used symbols, Lmax, total_bits = sum h[s]*cl[s],
+ *                          shortest length}.
+ * Canonical form (Sec. 4.2.2 and Algorithm 1, GenerateCW): at any prefix
+ * length l, the l-bit prefix of a longer code is numerically smaller than
+ * first[l]; first[Lmax] = 0 and first[l] = ceil((first[l+1] + cnt[l+1]) / 2);
+ * codes of one length ascend with the symbol id.  One used symbol gets the
+ * 1-bit code 0.
+ */
+typedef struct hf_codebook {
+  uint32_t alphabet;
+  uint8_t* cl;
+  uint64_t* cw;
+  uint64_t* first;
+  uint32_t* entry;
+  uint32_t* rev;
+  uint64_t* info;
+} hf_codebook;
+
+/* Workspace bytes that suffice for every entry point below on a stream of n
+ * symbols with this alphabet and chunk size (any reduce_log2). */
+size_t hf_workspace_bytes(uint64_t n, uint32_t alphabet, uint32_t chunk_symbols);
+
+/* Output words that always suffice without reading total_bits: a Huffman
+ * code averages at most ceil(log2 alphabet) + 1 bits per symbol. */
+uint64_t hf_bound_words(uint64_t n, uint32_t alphabet);
+
+/* The paper's reduction-factor rule (Sec. 4.3, Interface):
+ * floor(log2 beta) + r + 1 = log2(l_W) with l_W = 32 bits, for an average
+ * code length beta (bits per symbol), clamped to [1, 6].  A performance
+ * prior only; hf_encode's output does not depend on r. */
+uint32_t hf_reduction_factor(double beta);
+
+/* Human-readable name of a status code (static storage). */
+const char* hf_status_string(uint32_t code);
+
+/*
+ * Stage 1, histogramming (Sec. 4.1): d_hist[s] = number of i < n with
+ * d_sym[i] == s, for s < alphabet.  d_hist (uint32[alphabet]) is
+ * overwritten.  Symbols >= alphabet are not counted and raise
+ * HF_ERR_SYMBOL in *d_status.  Per-workgroup histograms are kept in LDS
+ * with several interleaved replicas and merged into d_hist with atomics.
+ */
+hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
+                       uint32_t* d_hist, void* d_ws, size_t ws_bytes, uint32_t* d_status,
+                       void* stream);
+
+/*
+ * Stages 2 and 3, codebook construction and canonization (Sec. 4.2,
+ * Algorithm 1): from d_hist (uint32[book->alphabet]) fill every array of
+ * *book (see hf_codebook).  Leaves are sorted by (count, symbol); code
+ * lengths come from parallel rounds that combine every subtree no heavier
+ * than the two lightest together, with ties taken leaf-first and then by
+ * rank, which is exactly the code a heap-based Huffman construction gives
+ * under that order; codewords are canonical as described above.  One
+ * workgroup builds the book; the tree lives in LDS when at most 4096
+ * symbols are used, else in the workspace.  Raises HF_ERR_CODELEN if a code
+ * would exceed 64 bits.
+ */
+hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
+                            size_t ws_bytes, uint32_t* d_status, void* stream);
+
+/*
+ * Stage 4, encoding (Sec. 4.3): the concatenation, in input order, of the
+ * codewords of d_sym[0..n) (MSB of each codeword first), written bit-dense
+ * into d_out: bit p of the stream is bit 31 - (p % 32) of d_out[p / 32]; the
+ * last word is zero padded; words past ceil(total_bits / 32) are untouched.
+ * d_chunk_bit_offsets (uint64[ceil(n / chunk_symbols) + 1]) receives the
+ * starting bit of every chunk of chunk_symbols symbols and, last, the total
+ * bit count, so that each chunk can be decoded independently (Sec. 3.1).
+ *   chunk_symbols: a power of two in [256, 65536].
+ *   reduce_log2:   r of the paper's ReduceShuffleMerge<M, r>; each lane
+ *                  merges 2^r consecutive codewords in registers before the
+ *                  workgroup-wide shuffle-merge; 1..6, or 0 for the library
+ *                  default.  The output does not depend on it.
+ * The result is bit-identical for every chunk_symbols and reduce_log2.
+ * Raises HF_ERR_SYMBOL for a symbol >= alphabet or with cl == 0, and
+ * HF_ERR_CAPACITY when total_bits > 32 * out_capacity_words (nothing is
+ * written at or past d_out[out_capacity_words]).
+ */
+hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t* d_out,
+                    uint64_t out_capacity_words, uint64_t* d_chunk_bit_offsets, void* d_ws,
+                    size_t ws_bytes, uint32_t* d_status, void* stream);
+
+/*
+ * Checker: decodes every chunk of d_out from its offset with the canonical
+ * First/Entry/rev tables (treeless decoding, Sec. 4.2.2) and compares it
+ * with d_sym_expected.  d_result (uint64[2]) receives {number of
+ * mismatching symbols (a chunk whose decoding ends off its next offset
+ * counts one more), index of the first mismatching symbol or n if none}.
+ * Raises HF_ERR_MISMATCH in *d_status when the count is not zero.
+ */
+hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets,
+                          uint64_t n, uint32_t sym_bytes, uint32_t chunk_symbols,
+                          const hf_codebook* book, const void* d_sym_expected,
+                          uint64_t* d_result, void* d_ws, size_t ws_bytes, uint32_t* d_status,
+                          void* stream);
+
+/*
+ * Profiling hook: for the next call of hf_histogram, hf_build_codebook or
+ * hf_encode made by this host thread, record hipEvent_t `before`
+ * immediately before that call's main kernel and `after` immediately after
+ * it, on the call's stream.  Either may be NULL to clear the hook.  One-shot.
+ */
+hf_status hf_time_next_main_kernel(void* before_event, void* after_event);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HF_H */

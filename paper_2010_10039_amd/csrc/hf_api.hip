@@ -1,0 +1,167 @@
+// hf_api.hip -- the extern "C" entry points of libhf: argument checks,
+// workspace sizing and kernel launches on the caller's stream.
+#include <math.h>
+#include <mutex>
+
+#include "hf_kernels.h"
+
+namespace {
+
+using hf::KernelTimer;
+
+thread_local KernelTimer t_timer;
+
+// Takes the armed one-shot timer (if any) for this call.
+KernelTimer take_timer() {
+  KernelTimer t = t_timer;
+  t_timer = KernelTimer{};
+  return t;
+}
+
+int num_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+uint32_t log2u(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+bool valid_symbols(uint32_t sym_bytes, uint32_t alphabet, uint64_t n) {
+  if (sym_bytes != 1 && sym_bytes != 2) return false;
+  if (alphabet == 0 || alphabet > 65536u) return false;
+  if (sym_bytes == 1 && alphabet > 256u) return false;
+  if (n >= (1ull << 32)) return false;
+  return true;
+}
+
+bool valid_book(const hf_codebook* b) {
+  return b && b->alphabet >= 1 && b->alphabet <= 65536u && b->cl && b->cw && b->first && b->entry &&
+         b->rev && b->info;
+}
+
+bool valid_chunk(uint32_t chunk) { return is_pow2(chunk) && chunk >= 256u && chunk <= 65536u; }
+
+uint32_t effective_r(uint32_t r) { return r == 0 ? (uint32_t)hf::kEncDefaultR : r; }
+
+hf_status launch_result(hipError_t e) { return e == hipSuccess ? HF_OK : HF_ERR_LAUNCH; }
+
+}  // namespace
+
+extern "C" {
+
+size_t hf_workspace_bytes(uint64_t n, uint32_t alphabet, uint32_t chunk_symbols) {
+  (void)chunk_symbols;
+  size_t enc = 0;
+  for (uint32_t r = hf::kEncMinR; r <= (uint32_t)hf::kEncMaxR; ++r) {
+    const size_t b = hf::encode_workspace_bytes(n, r);
+    if (b > enc) enc = b;
+  }
+  const size_t cb = hf::codebook_workspace_bytes(alphabet);
+  const size_t need = enc > cb ? enc : cb;
+  return need < 256 ? 256 : need;
+}
+
+uint64_t hf_bound_words(uint64_t n, uint32_t alphabet) {
+  const uint64_t bits_per = (uint64_t)log2u(alphabet > 0 ? alphabet : 1) + 1;
+  return (n * bits_per + 31) / 32 + 1;
+}
+
+uint32_t hf_reduction_factor(double beta) {
+  if (!(beta >= 1.0)) beta = 1.0;
+  const int fl = (int)floor(log2(beta));
+  int r = 5 - fl - 1;  // floor(log2 beta) + r + 1 = log2(32) = 5
+  if (r < hf::kEncMinR) r = hf::kEncMinR;
+  if (r > hf::kEncMaxR) r = hf::kEncMaxR;
+  return (uint32_t)r;
+}
+
+const char* hf_status_string(uint32_t code) {
+  switch (code) {
+    case HF_OK: return "ok";
+    case HF_ERR_ARG: return "invalid argument";
+    case HF_ERR_WORKSPACE: return "workspace missing or too small";
+    case HF_ERR_LAUNCH: return "kernel launch failed";
+    case HF_ERR_SYMBOL: return "symbol outside the alphabet or without a code";
+    case HF_ERR_CAPACITY: return "output capacity exceeded";
+    case HF_ERR_CODELEN: return "code length above 64 bits";
+    case HF_ERR_MISMATCH: return "decoded stream differs from the input";
+    case HF_ERR_INTERNAL: return "internal bound exceeded";
+    default: return "unknown status";
+  }
+}
+
+hf_status hf_time_next_main_kernel(void* before_event, void* after_event) {
+  t_timer.ev_before = (hipEvent_t)before_event;
+  t_timer.ev_after = (hipEvent_t)after_event;
+  return HF_OK;
+}
+
+hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
+                       uint32_t* d_hist, void* d_ws, size_t ws_bytes, uint32_t* d_status,
+                       void* stream) {
+  (void)d_ws;
+  (void)ws_bytes;
+  const KernelTimer timer = take_timer();
+  if (!valid_symbols(sym_bytes, alphabet, n) || !d_hist || !d_status || (n > 0 && !d_sym))
+    return HF_ERR_ARG;
+  if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
+  return launch_result(hf::launch_histogram(d_sym, n, sym_bytes, alphabet, d_hist, d_status, num_cus(),
+                                            (hipStream_t)stream, timer));
+}
+
+hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
+                            size_t ws_bytes, uint32_t* d_status, void* stream) {
+  const KernelTimer timer = take_timer();
+  if (!d_hist || !valid_book(book) || !d_status) return HF_ERR_ARG;
+  const size_t need = hf::codebook_workspace_bytes(book->alphabet);
+  if (need > 0 && (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255))) return HF_ERR_WORKSPACE;
+  return launch_result(hf::launch_codebook(d_hist, *book, d_ws, ws_bytes, d_status, (hipStream_t)stream, timer));
+}
+
+hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t* d_out,
+                    uint64_t out_capacity_words, uint64_t* d_chunk_bit_offsets, void* d_ws,
+                    size_t ws_bytes, uint32_t* d_status, void* stream) {
+  const KernelTimer timer = take_timer();
+  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
+      !d_chunk_bit_offsets || !d_status || (n > 0 && (!d_sym || !d_out)))
+    return HF_ERR_ARG;
+  if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
+  if (reduce_log2 > (uint32_t)hf::kEncMaxR) return HF_ERR_ARG;
+  const uint32_t r = effective_r(reduce_log2);
+  const size_t need = hf::encode_workspace_bytes(n, r);
+  if (n > 0 && (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255))) return HF_ERR_WORKSPACE;
+  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, d_out,
+                                         out_capacity_words, d_chunk_bit_offsets, d_ws, d_status,
+                                         num_cus(), (hipStream_t)stream, timer));
+}
+
+hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets, uint64_t n,
+                          uint32_t sym_bytes, uint32_t chunk_symbols, const hf_codebook* book,
+                          const void* d_sym_expected, uint64_t* d_result, void* d_ws,
+                          size_t ws_bytes, uint32_t* d_status, void* stream) {
+  (void)d_ws;
+  (void)ws_bytes;
+  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
+      !d_chunk_bit_offsets || !d_result || !d_status || (n > 0 && (!d_out || !d_sym_expected)))
+    return HF_ERR_ARG;
+  return launch_result(hf::launch_decode_check(d_out, d_chunk_bit_offsets, n, sym_bytes,
+                                               log2u(chunk_symbols), *book, d_sym_expected, d_result,
+                                               d_status, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,477 @@
+// hf_codebook.hip -- stages 2 and 3: parallel Huffman code lengths and
+// canonical codewords (Sec. 4.2, Algorithm 1 of the paper).
+//
+// One workgroup of 1024 lanes builds the whole book.  The paper runs its
+// construction as cooperative grid-wide kernels over global memory; a
+// codebook of a few thousand used symbols fits one gfx950 workgroup's LDS
+// (160 KiB), where a barrier costs ~100 cycles instead of a grid sync, so the
+// tree lives in LDS whenever at most kCbLdsMaxUsed symbols are used and in
+// the workspace otherwise (same code, instantiated for both).
+//
+// Steps:
+//  1. compaction: used symbols in ascending symbol order get compact index u;
+//     unused symbols receive cl = cw = 0 at once;
+//  2. sort leaves by (count, u) -- u preserves symbol order -- with a bitonic
+//     network on 48-bit keys (count << 16 | u); the paper sorts with Thrust;
+//  3. GenerateCL: rounds of the parallel two-queue construction.  t = sum of
+//     the two lightest available nodes (leaf before internal on equal
+//     weight); every unconsumed leaf with weight <= t and every queued
+//     internal node are merged by key (Merge Path: each element's output
+//     position is its own index plus a binary search in the other run);
+//     consecutive pairs meld into new internal nodes; an odd last node waits
+//     for the next round.  This consumes nodes in exactly the order of a heap
+//     keyed (weight, leaf-first, rank), so the lengths equal that heap's.
+//     The paper's strict "< t" threshold and its leader-pointer updates are
+//     replaced by "<= t" and one parent link per node;
+//  4. depths of internal nodes by pointer jumping over parent links
+//     (log2 depth steps); cl(leaf) = depth(parent) + 1;
+//  5. GenerateCW + canonization: counts per length; First and Entry; the
+//     rank of each symbol among equal lengths in symbol order from wave
+//     ballots (a stable counting sort by length), giving cw = first[l] + rank
+//     and rev[entry[l] + rank] = symbol.
+#include "hf_device.h"
+#include "hf_kernels.h"
+
+namespace hf {
+
+namespace {
+
+constexpr uint32_t kMaxLen = HF_MAX_CODELEN;
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline uint32_t pow2_ceil(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Global-memory layout of the tree when more than kCbLdsMaxUsed symbols
+// are used (ids need 32 bits there).
+struct GlobalLayout {
+  size_t key, iw, mw, mid, par, usym, clu, dA, dB, nA, nB, total;
+};
+
+__host__ __device__ inline GlobalLayout global_layout(uint32_t A) {
+  GlobalLayout L;
+  size_t o = 0;
+  const uint32_t P = pow2_ceil(A);
+  L.key = o;  o += align256((size_t)P * 8);
+  L.iw = o;   o += align256((size_t)A * 8);
+  L.mw = o;   o += align256((size_t)A * 8);
+  L.mid = o;  o += align256((size_t)A * 4);
+  L.par = o;  o += align256((size_t)A * 8);
+  L.usym = o; o += align256((size_t)A * 4);
+  L.clu = o;  o += align256((size_t)A);
+  L.dA = o;   o += align256((size_t)A * 2);
+  L.dB = o;   o += align256((size_t)A * 2);
+  L.nA = o;   o += align256((size_t)A * 4);
+  L.nB = o;   o += align256((size_t)A * 4);
+  L.total = o;
+  return L;
+}
+
+template <typename IdT>
+struct Tree {
+  uint64_t* key;   // [P] leaves, sorted by (count << 16 | u); padding ~0
+  uint64_t* iw;    // [m-1] internal node weights, creation order
+  uint64_t* mw;    // [m] merged sequence of the current round: weights
+  IdT* mid;        // [m] merged sequence: node ids (leaf i -> i, internal k -> m+k)
+  IdT* par;        // [2m-1] parent internal index of every node id
+  IdT* usym;       // [m] compact index -> symbol
+  uint8_t* clu;    // [m] compact index -> code length
+  uint16_t* dA;    // [m-1] depth ping-pong
+  uint16_t* dB;
+  IdT* nA;         // [m-1] jump-pointer ping-pong
+  IdT* nB;
+};
+
+struct Shared {
+  uint32_t wtot[kCbWaves];
+  uint32_t cnt[kMaxLen + 1];
+  uint32_t cntw[kCbWaves][kMaxLen + 1];
+  uint64_t first[kMaxLen + 1];
+  uint32_t entry[kMaxLen + 1];
+  uint64_t total;
+  uint32_t lc, ih, it, a, b, done;
+  uint32_t lmax, lmin;
+};
+
+// Per-wave aggregation of equal values before one LDS atomic per distinct
+// value: lanes with the same code length add their count in one go.
+__device__ __forceinline__ void count_lengths(uint32_t l, bool valid, uint32_t* cnt) {
+  uint64_t pending = __ballot(valid);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lv = __shfl(l, leader, kWave);
+    const uint64_t mask = __ballot(valid && l == lv);
+    if (lane_id() == leader) atomicAdd(&cnt[lv], (uint32_t)__popcll(mask));
+    pending &= ~mask;
+  }
+}
+
+template <typename IdT>
+__device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
+                                           uint32_t A, uint32_t s_lo, uint32_t s_hi, uint32_t base,
+                                           uint32_t m, const hf_codebook& book, uint32_t* status) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t bd = kCbThreads;
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t wave = tid / kWave;
+
+  // ---- 1. compaction -----------------------------------------------------
+  {
+    uint32_t u = base;
+    for (uint32_t s = s_lo; s < s_hi; ++s) {
+      const uint32_t h = hist[s];
+      if (h) {
+        t.key[u] = ((uint64_t)h << 16) | u;
+        t.usym[u] = (IdT)s;
+        ++u;
+      } else {
+        book.cl[s] = 0;
+        book.cw[s] = 0;
+      }
+    }
+  }
+  const uint32_t P = pow2_ceil(m > 0 ? m : 1);
+  for (uint32_t i = m + tid; i < P; i += bd) t.key[i] = ~0ull;
+  for (uint32_t l = tid; l <= kMaxLen; l += bd) sh.cnt[l] = 0;
+  if (tid == 0) {
+    sh.total = 0;
+    sh.lmax = 0;
+    sh.lmin = 0xFFFFFFFFu;
+  }
+  __syncthreads();
+
+  if (m <= 1) {
+    // no tree: an empty book, or one symbol with the 1-bit code 0
+    for (uint32_t l = tid; l <= kMaxLen; l += bd) {
+      book.first[l] = 0;
+      book.entry[l] = (m == 1 && l >= 2) ? 1u : 0u;
+    }
+    if (tid == 0) {
+      uint64_t h0 = 0;
+      if (m == 1) {
+        const uint32_t s = (uint32_t)t.usym[0];
+        h0 = t.key[0] >> 16;
+        book.cl[s] = 1;
+        book.cw[s] = 0;
+        book.rev[0] = s;
+      }
+      book.info[0] = m;
+      book.info[1] = m;
+      book.info[2] = h0;
+      book.info[3] = m;
+    }
+    return;
+  }
+
+  // ---- 2. bitonic sort of key[0, P) ascending ------------------------------
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < P / 2; i += bd) {
+        const uint32_t l = 2 * j * (i / j) + (i & (j - 1));
+        const uint32_t r = l + j;
+        const bool up = (l & k) == 0;
+        const uint64_t x = t.key[l], y = t.key[r];
+        if ((x > y) == up) {
+          t.key[l] = y;
+          t.key[r] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- 3. GenerateCL rounds ------------------------------------------------
+  if (tid == 0) {
+    sh.lc = 0;
+    sh.ih = 0;
+    sh.it = 0;
+  }
+  __syncthreads();
+  for (uint32_t round = 0;; ++round) {
+    if (tid == 0) {
+      const uint32_t lc = sh.lc, ih = sh.ih, it = sh.it;
+      if ((m - lc) + (it - ih) <= 1) {
+        sh.done = 1;
+      } else if (round >= m) {
+        // every round creates at least one node, so m - 1 rounds suffice
+        raise_status(status, HF_ERR_INTERNAL);
+        sh.done = 1;
+      } else {
+        // the two lightest available nodes, leaf first on equal weight
+        uint32_t li = lc, ii = ih;
+        uint64_t wsum = 0;
+        for (int p = 0; p < 2; ++p) {
+          const bool leaf = li < m && (ii >= it || (t.key[li] >> 16) <= t.iw[ii]);
+          wsum += leaf ? (t.key[li++] >> 16) : t.iw[ii++];
+        }
+        // leaves with weight <= t: upper bound in the sorted run [lc, m)
+        uint32_t lo = lc, hi = m;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if ((t.key[md] >> 16) <= wsum) lo = md + 1;
+          else hi = md;
+        }
+        sh.a = lo - lc;
+        sh.b = it - ih;
+        sh.done = 0;
+      }
+    }
+    __syncthreads();
+    if (sh.done) break;
+    const uint32_t lc = sh.lc, ih = sh.ih, it = sh.it, a = sh.a, b = sh.b;
+    const uint32_t total = a + b, pairs = total >> 1;
+    // Merge Path: leaves precede internal nodes of equal weight
+    for (uint32_t j = tid; j < a; j += bd) {
+      const uint64_t w = t.key[lc + j] >> 16;
+      uint32_t lo = ih, hi = it;
+      while (lo < hi) {
+        const uint32_t md = (lo + hi) >> 1;
+        if (t.iw[md] < w) lo = md + 1;
+        else hi = md;
+      }
+      const uint32_t pos = j + (lo - ih);
+      t.mw[pos] = w;
+      t.mid[pos] = (IdT)(lc + j);
+    }
+    for (uint32_t q = tid; q < b; q += bd) {
+      const uint64_t w = t.iw[ih + q];
+      uint32_t lo = lc, hi = lc + a;
+      while (lo < hi) {
+        const uint32_t md = (lo + hi) >> 1;
+        if ((t.key[md] >> 16) <= w) lo = md + 1;
+        else hi = md;
+      }
+      const uint32_t pos = q + (lo - lc);
+      t.mw[pos] = w;
+      t.mid[pos] = (IdT)(m + ih + q);
+    }
+    __syncthreads();
+    // Meld consecutive pairs
+    for (uint32_t p = tid; p < pairs; p += bd) {
+      const uint32_t k = it + p;
+      t.iw[k] = t.mw[2 * p] + t.mw[2 * p + 1];
+      t.par[t.mid[2 * p]] = (IdT)k;
+      t.par[t.mid[2 * p + 1]] = (IdT)k;
+    }
+    if (tid == 0) {
+      uint32_t lcn = lc + a, ihn = ih + b;
+      if (total & 1) {
+        if ((uint32_t)t.mid[total - 1] < m) lcn -= 1;
+        else ihn -= 1;
+      }
+      sh.lc = lcn;
+      sh.ih = ihn;
+      sh.it = it + pairs;
+    }
+    __syncthreads();
+  }
+
+  // ---- 4. depths by pointer jumping ----------------------------------------
+  const uint32_t nint = m - 1, root = m - 2;
+  for (uint32_t k = tid; k < nint; k += bd) {
+    t.dA[k] = (k == root) ? 0 : 1;
+    t.nA[k] = (IdT)((k == root) ? root : (uint32_t)t.par[m + k]);
+  }
+  __syncthreads();
+  uint16_t* dc = t.dA;
+  uint16_t* dn = t.dB;
+  IdT* nc = t.nA;
+  IdT* nn = t.nB;
+  for (int step = 0;; ++step) {
+    int active = 0;
+    for (uint32_t k = tid; k < nint; k += bd) {
+      const IdT x = nc[k];
+      const uint32_t d = (uint32_t)dc[k] + dc[x];
+      dn[k] = (uint16_t)(d < 0xFFFFu ? d : 0xFFFFu);
+      const IdT y = nc[x];
+      nn[k] = y;
+      active |= ((uint32_t)y != root);
+    }
+    uint16_t* td = dc; dc = dn; dn = td;
+    IdT* tn = nc; nc = nn; nn = tn;
+    if (!__syncthreads_or(active)) break;
+    if (step >= 32) {  // depth < 2^32 needs at most 32 doublings
+      if (tid == 0) raise_status(status, HF_ERR_INTERNAL);
+      break;
+    }
+  }
+
+  // ---- 5a. leaf lengths, counts per length, total bits ----------------------
+  uint64_t bits = 0;
+  uint32_t my_max = 0, my_min = 0xFFFFFFFFu;
+  for (uint32_t i0 = 0; i0 < m; i0 += bd) {
+    const uint32_t i = i0 + tid;
+    const bool valid = i < m;
+    uint32_t l = 0;
+    if (valid) {
+      const uint64_t kk = t.key[i];
+      const uint32_t u = (uint32_t)(kk & 0xFFFFu);
+      l = (uint32_t)dc[t.par[i]] + 1;
+      bits += (kk >> 16) * l;
+      my_max = max(my_max, l);
+      my_min = min(my_min, l);
+      if (l > kMaxLen) l = kMaxLen;  // flagged below; keeps indexes in range
+      t.clu[u] = (uint8_t)l;
+      book.cl[(uint32_t)t.usym[u]] = (uint8_t)l;
+    }
+    count_lengths(l, valid, sh.cnt);
+  }
+  bits = wave_sum_u64(bits);
+  my_max = wave_max_u32(my_max);
+  if (lane == 0) {
+    atomicAdd((unsigned long long*)&sh.total, (unsigned long long)bits);
+    atomicMax(&sh.lmax, my_max);
+  }
+  if (my_min != 0xFFFFFFFFu) atomicMin(&sh.lmin, my_min);
+  __syncthreads();
+
+  // ---- 5b. First and Entry ------------------------------------------------
+  if (tid == 0) {
+    uint32_t L = sh.lmax;
+    if (L > kMaxLen) {
+      raise_status(status, HF_ERR_CODELEN);
+      L = kMaxLen;
+    }
+    for (uint32_t l = 0; l <= kMaxLen; ++l) sh.first[l] = 0;
+    for (int l = (int)L - 1; l >= 1; --l) sh.first[l] = (sh.first[l + 1] + sh.cnt[l + 1] + 1) >> 1;
+    uint32_t below = 0;
+    for (uint32_t l = 0; l <= kMaxLen; ++l) {
+      sh.entry[l] = below;
+      if (l >= 1) below += sh.cnt[l];
+    }
+    book.info[0] = m;
+    book.info[1] = sh.lmax;
+    book.info[2] = sh.total;
+    book.info[3] = sh.lmin;
+  }
+  __syncthreads();
+  for (uint32_t l = tid; l <= kMaxLen; l += bd) {
+    book.first[l] = sh.first[l];
+    book.entry[l] = sh.entry[l];
+  }
+
+  // ---- 5c. rank within each length in symbol order -------------------------
+  const uint32_t seg = ((m + kCbThreads - 1) / kCbThreads) * kWave;
+  const uint32_t sbeg = min(m, wave * seg), send = min(m, sbeg + seg);
+  uint32_t creg = 0;  // lane l-1 counts length l
+  for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
+    const uint32_t u = u0 + lane;
+    const bool valid = u < send;
+    const uint32_t l = valid ? t.clu[u] : 0;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t lv = __shfl(l, leader, kWave);
+      const uint64_t mask = __ballot(valid && l == lv);
+      if (lane == lv - 1) creg += (uint32_t)__popcll(mask);
+      pending &= ~mask;
+    }
+  }
+  sh.cntw[wave][lane + 1] = creg;
+  __syncthreads();
+  if (tid >= 1 && tid <= kMaxLen) {
+    uint32_t run = sh.entry[tid];
+    for (int w = 0; w < kCbWaves; ++w) {
+      const uint32_t c = sh.cntw[w][tid];
+      sh.cntw[w][tid] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  uint32_t breg = sh.cntw[wave][lane + 1];  // next rev slot of length lane+1
+  for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
+    const uint32_t u = u0 + lane;
+    const bool valid = u < send;
+    const uint32_t l = valid ? t.clu[u] : 0;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t lv = __shfl(l, leader, kWave);
+      const uint64_t mask = __ballot(valid && l == lv);
+      const uint32_t slot0 = __shfl(breg, (int)lv - 1, kWave);
+      if (valid && l == lv) {
+        const uint32_t pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
+        const uint32_t s = (uint32_t)t.usym[u];
+        book.rev[pos] = s;
+        book.cw[s] = sh.first[lv] + (pos - sh.entry[lv]);
+      }
+      if (lane == lv - 1) breg += (uint32_t)__popcll(mask);
+      pending &= ~mask;
+    }
+  }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kCbThreads) void codebook_kernel(const uint32_t* __restrict__ hist,
+                                                              hf_codebook book, char* ws,
+                                                              uint32_t* status) {
+  __shared__ Shared sh;
+  __shared__ uint64_t s_key[kCbLdsMaxUsed];
+  __shared__ uint64_t s_iw[kCbLdsMaxUsed];
+  __shared__ uint64_t s_mw[kCbLdsMaxUsed];  // also holds the depth arrays after the rounds
+  __shared__ uint16_t s_mid[kCbLdsMaxUsed];
+  __shared__ uint16_t s_par[2 * kCbLdsMaxUsed];
+  __shared__ uint16_t s_usym[kCbLdsMaxUsed];
+  __shared__ uint8_t s_clu[kCbLdsMaxUsed];
+
+  const uint32_t A = book.alphabet;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (A + kCbThreads - 1) / kCbThreads;
+  const uint32_t s_lo = min(A, tid * per), s_hi = min(A, s_lo + per);
+  uint32_t c = 0;
+  for (uint32_t s = s_lo; s < s_hi; ++s) c += (hist[s] != 0);
+  uint32_t m;
+  const uint32_t base = block_exclusive_scan<kCbWaves>(c, sh.wtot, &m);
+
+  if (m <= kCbLdsMaxUsed) {
+    Tree<uint16_t> t;
+    t.key = s_key;
+    t.iw = s_iw;
+    t.mw = s_mw;
+    t.mid = s_mid;
+    t.par = s_par;
+    t.usym = s_usym;
+    t.clu = s_clu;
+    t.dA = (uint16_t*)s_mw;
+    t.dB = t.dA + kCbLdsMaxUsed;
+    t.nA = t.dB + kCbLdsMaxUsed;
+    t.nB = t.nA + kCbLdsMaxUsed;
+    build_book(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+  } else {
+    const GlobalLayout L = global_layout(A);
+    Tree<uint32_t> t;
+    t.key = (uint64_t*)(ws + L.key);
+    t.iw = (uint64_t*)(ws + L.iw);
+    t.mw = (uint64_t*)(ws + L.mw);
+    t.mid = (uint32_t*)(ws + L.mid);
+    t.par = (uint32_t*)(ws + L.par);
+    t.usym = (uint32_t*)(ws + L.usym);
+    t.clu = (uint8_t*)(ws + L.clu);
+    t.dA = (uint16_t*)(ws + L.dA);
+    t.dB = (uint16_t*)(ws + L.dB);
+    t.nA = (uint32_t*)(ws + L.nA);
+    t.nB = (uint32_t*)(ws + L.nB);
+    build_book(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+  }
+}
+
+size_t codebook_workspace_bytes(uint32_t alphabet) {
+  return alphabet > kCbLdsMaxUsed ? global_layout(alphabet).total : 0;
+}
+
+hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
+                           uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
+  (void)ws_bytes;
+  timer.before(stream);
+  codebook_kernel<<<1, kCbThreads, 0, stream>>>(hist, book, (char*)ws, status);
+  hipError_t e = hipGetLastError();
+  timer.after(stream);
+  return e;
+}
+
+}  // namespace hf

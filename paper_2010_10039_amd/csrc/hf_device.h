@@ -1,0 +1,80 @@
+// hf_device.h -- device-side helpers shared by the libhf kernels (gfx950,
+// wave64).  Internal to libhf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hf.h"
+
+namespace hf {
+
+constexpr int kWave = 64;
+
+// First error wins: only a zero status is replaced.
+__device__ __forceinline__ void raise_status(uint32_t* status, uint32_t code) {
+  atomicCAS(status, 0u, code);
+}
+
+// Relaxed agent-scope atomics: visible across all XCDs of the device without
+// ordering any other memory.  Used for self-contained 64-bit records.
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Bits of lanes strictly below this one.
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, kWave);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
+  return v;
+}
+
+// Exclusive scan over the whole workgroup (blockDim.x = 64 * NW).  `wtot`
+// is an LDS array of NW words; *total receives the workgroup sum.  Contains
+// one barrier; the caller must not overwrite `wtot` until every thread has
+// returned (i.e. until its next barrier).
+template <int NW>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wtot, uint32_t* total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  uint32_t inc = wave_inclusive_scan(v);
+  if (lane == kWave - 1) wtot[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    uint32_t t = wtot[i];
+    pre += (i < w) ? t : 0u;
+    tot += t;
+  }
+  *total = tot;
+  return pre + inc - v;
+}
+
+}  // namespace hf

@@ -1,0 +1,171 @@
+// hf_histogram.hip -- stage 1, histogramming (Sec. 4.1 of the paper).
+//
+// The paper builds on Gomez-Luna et al.: every thread block keeps private
+// replicated sub-histograms in shared memory, updates them with atomics, and
+// the block results are merged into one global histogram.  On gfx950:
+//  - each workgroup reads one contiguous slab of the input with 16-byte
+//    vector loads (several in flight per lane), so HBM sees long streams;
+//  - R replicas of the bin window live in LDS interleaved per bin
+//    (bin b, replica r at word b*R + r), lane l updating replica l % R, so
+//    lanes hitting the same bin land on R different banks;
+//  - at the end every non-zero bin is added to the global histogram with
+//    one global atomic, so peaked data costs a few hundred atomics per
+//    workgroup, not one per bin;
+//  - a bin window [lo, lo + W) lets alphabets too large for LDS run in
+//    several passes over the input.
+#include <algorithm>
+
+#include "hf_device.h"
+#include "hf_kernels.h"
+
+namespace hf {
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < count; i += (uint64_t)gridDim.x * blockDim.x) p[i] = value;
+}
+
+__global__ void fill_u64_kernel(uint64_t* __restrict__ p, uint64_t count, uint64_t value) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < count; i += (uint64_t)gridDim.x * blockDim.x) p[i] = value;
+}
+
+template <int SB>
+__device__ __forceinline__ uint32_t sym_load(const void* p, uint64_t i) {
+  if (SB == 1) return ((const uint8_t*)p)[i];
+  return ((const uint16_t*)p)[i];
+}
+
+// Count one symbol into the LDS window.
+__device__ __forceinline__ void hist_count(uint32_t* sub, uint32_t s, uint32_t lo, uint32_t W,
+                                           uint32_t A, uint32_t R, uint32_t rep, bool& bad) {
+  uint32_t b = s - lo;  // wraps for s < lo
+  if (b < W) atomicAdd(&sub[b * R + rep], 1u);
+  bad |= (s >= A);
+}
+
+template <int SB>
+__device__ __forceinline__ void hist_count_vec(uint32_t* sub, uint4 v, uint32_t lo, uint32_t W,
+                                               uint32_t A, uint32_t R, uint32_t rep, bool& bad) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (SB == 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) hist_count(sub, (w[k] >> (8 * j)) & 0xFFu, lo, W, A, R, rep, bad);
+    } else {
+      hist_count(sub, w[k] & 0xFFFFu, lo, W, A, R, rep, bad);
+      hist_count(sub, w[k] >> 16, lo, W, A, R, rep, bad);
+    }
+  }
+}
+
+// One launch counts bins [lo, lo + W) of a slab-partitioned input.  The
+// first `head` symbols (up to the first 16-byte boundary) and the tail after
+// the last whole vector are counted by workgroup 0 with scalar loads.
+template <int SB>
+__global__ __launch_bounds__(kHistThreads) void histogram_kernel(
+    const void* __restrict__ sym, uint64_t n, uint64_t head, uint32_t A, uint32_t lo, uint32_t W,
+    uint32_t R, uint32_t* __restrict__ hist, uint32_t* __restrict__ status) {
+  extern __shared__ uint32_t sub[];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < W * R; i += blockDim.x) sub[i] = 0;
+  __syncthreads();
+
+  constexpr uint32_t kPerVec = 16 / SB;
+  const uint32_t rep = tid & (R - 1);
+  bool bad = false;
+  const uint64_t nbody = (n - head) / kPerVec;
+  const uint4* body = (const uint4*)((const char*)sym + head * SB);
+  const uint64_t per = (nbody + gridDim.x - 1) / gridDim.x;
+  const uint64_t beg = (uint64_t)blockIdx.x * per;
+  const uint64_t end = min(nbody, beg + per);
+
+  uint64_t v = beg + tid;
+  constexpr int kUnroll = 4;
+  for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < end; v += kUnroll * (uint64_t)blockDim.x) {
+    uint4 q[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) hist_count_vec<SB>(sub, q[u], lo, W, A, R, rep, bad);
+  }
+  for (; v < end; v += blockDim.x) hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
+
+  if (blockIdx.x == 0) {
+    for (uint64_t i = tid; i < head; i += blockDim.x) hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+    for (uint64_t i = head + nbody * kPerVec + tid; i < n; i += blockDim.x)
+      hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+  }
+  __syncthreads();
+
+  for (uint32_t b = tid; b < W; b += blockDim.x) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+    if (c) atomicAdd(&hist[lo + b], c);
+  }
+  if (bad) raise_status(status, HF_ERR_SYMBOL);
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (count + 255) / 256);
+  fill_u32_kernel<<<blocks, 256, 0, stream>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (count + 255) / 256);
+  fill_u64_kernel<<<blocks, 256, 0, stream>>>(p, count, value);
+  return hipGetLastError();
+}
+
+// LDS per workgroup: up to 64 KiB for the replicated window (two
+// workgroups of 16 waves per CU); alphabets whose single replica needs more
+// use windows of up to 32768 bins (128 KiB, one workgroup per CU).
+static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
+  const uint32_t budget = 64u << 10;
+  if (A * 4u <= budget) {
+    uint32_t r = 1;
+    while (r < 16 && A * 4u * (r * 2) <= budget) r *= 2;
+    *W = A;
+    *R = r;
+  } else {
+    *W = A < 32768u ? A : 32768u;
+    *R = 1;
+  }
+}
+
+hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t A,
+                            uint32_t* hist, uint32_t* status, int num_cus, hipStream_t stream,
+                            const KernelTimer& timer) {
+  hipError_t e = launch_fill_u32(hist, A, 0u, stream);
+  if (e != hipSuccess) return e;
+  uint32_t W, R;
+  hist_plan(A, &W, &R);
+  const size_t lds = (size_t)W * R * sizeof(uint32_t);
+  const uint64_t per_vec = 16 / sym_bytes;
+  const uintptr_t addr = (uintptr_t)sym;
+  uint64_t head = ((16 - (addr & 15)) & 15) / sym_bytes;
+  if (head > n) head = n;
+  const uint64_t nbody = (n - head) / per_vec;
+  // enough vectors per workgroup to amortize the LDS clear and flush
+  const uint64_t want = (nbody + 4ull * kHistThreads * 8 - 1) / (4ull * kHistThreads * 8);
+  const uint32_t wgs_per_cu = (lds <= (64u << 10)) ? 2u : 1u;
+  uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)num_cus * wgs_per_cu, want > 0 ? want : 1);
+  timer.before(stream);
+  for (uint32_t lo = 0; lo < A; lo += W) {
+    const uint32_t w = std::min(W, A - lo);
+    if (sym_bytes == 1)
+      histogram_kernel<1><<<grid, kHistThreads, lds, stream>>>(sym, n, head, A, lo, w, R, hist, status);
+    else
+      histogram_kernel<2><<<grid, kHistThreads, lds, stream>>>(sym, n, head, A, lo, w, R, hist, status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  timer.after(stream);
+  return hipSuccess;
+}
+
+}  // namespace hf

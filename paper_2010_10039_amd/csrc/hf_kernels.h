@@ -1,0 +1,67 @@
+// hf_kernels.h -- host-side launchers of the libhf kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hf.h"
+
+namespace hf {
+
+constexpr int kHistThreads = 1024;
+constexpr int kCbThreads = 1024;
+constexpr int kCbWaves = kCbThreads / 64;
+constexpr uint32_t kCbLdsMaxUsed = 4096;  // codebook tree kept in LDS up to this many used symbols
+constexpr int kEncThreads = 256;
+constexpr int kEncWaves = kEncThreads / 64;
+constexpr int kEncMinR = 1;
+constexpr int kEncMaxR = 6;
+constexpr int kEncDefaultR = 4;
+constexpr uint32_t kPackedMaxLen = 27;        // cw << 5 | cl fits 32 bits
+constexpr uint32_t kPackedMaxAlphabet = 16384;  // packed table kept in LDS up to this alphabet
+
+// Records a pair of events around one kernel launch when armed.
+struct KernelTimer {
+  hipEvent_t ev_before = nullptr;
+  hipEvent_t ev_after = nullptr;
+  void before(hipStream_t s) const {
+    if (ev_before) (void)hipEventRecord(ev_before, s);
+  }
+  void after(hipStream_t s) const {
+    if (ev_after) (void)hipEventRecord(ev_after, s);
+  }
+};
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t stream);
+
+hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
+                            uint32_t* hist, uint32_t* status, int num_cus, hipStream_t stream,
+                            const KernelTimer& timer);
+
+// Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
+// symbols are used.
+size_t codebook_workspace_bytes(uint32_t alphabet);
+
+hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
+                           uint32_t* status, hipStream_t stream, const KernelTimer& timer);
+
+struct EncodeWorkspace {
+  uint32_t* ticket;    // 1 word
+  uint64_t* lookback;  // [ntiles] {flag:2 | value:62}
+  uint64_t* tails;     // [ntiles] {valid:32 | last 32 content bits}
+};
+size_t encode_workspace_bytes(uint64_t n, uint32_t r);
+EncodeWorkspace encode_workspace_layout(void* ws, uint64_t n, uint32_t r);
+
+hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
+                         uint32_t chunk_log2, uint32_t r, uint32_t* out, uint64_t cap_words,
+                         uint64_t* offsets, void* ws, uint32_t* status, int num_cus,
+                         hipStream_t stream, const KernelTimer& timer);
+
+hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
+                               uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,
+                               const void* expected, uint64_t* result, uint32_t* status,
+                               hipStream_t stream);
+
+}  // namespace hf

@@ -1,0 +1,277 @@
+"""Python binding of libhf (include/hf.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors on a ROCm device; calls enqueue work on torch's
+current stream and return without synchronizing.  Every step of the encoding
+runs in the HIP kernels of libhf.so; if the library is not built, importing
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhf.so")
+
+HF_OK = 0
+HF_ERR_ARG = 1
+HF_ERR_WORKSPACE = 2
+HF_ERR_LAUNCH = 3
+HF_ERR_SYMBOL = 16
+HF_ERR_CAPACITY = 17
+HF_ERR_CODELEN = 18
+HF_ERR_MISMATCH = 19
+HF_ERR_INTERNAL = 20
+MAX_CODELEN = 64
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(
+        f"{_LIB_PATH} is not built; run `python -m paper_2010_10039_amd.build` "
+        "(the encoder has no CPU fallback)")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+
+class hf_codebook(ctypes.Structure):
+    _fields_ = [
+        ("alphabet", ctypes.c_uint32),
+        ("cl", ctypes.c_void_p),
+        ("cw", ctypes.c_void_p),
+        ("first", ctypes.c_void_p),
+        ("entry", ctypes.c_void_p),
+        ("rev", ctypes.c_void_p),
+        ("info", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+
+_lib.hf_workspace_bytes.argtypes = [_U64, _U32, _U32]
+_lib.hf_workspace_bytes.restype = _SZ
+_lib.hf_bound_words.argtypes = [_U64, _U32]
+_lib.hf_bound_words.restype = _U64
+_lib.hf_reduction_factor.argtypes = [ctypes.c_double]
+_lib.hf_reduction_factor.restype = _U32
+_lib.hf_status_string.argtypes = [_U32]
+_lib.hf_status_string.restype = ctypes.c_char_p
+_lib.hf_time_next_main_kernel.argtypes = [_P, _P]
+_lib.hf_time_next_main_kernel.restype = ctypes.c_int
+_lib.hf_histogram.argtypes = [_P, _U64, _U32, _U32, _P, _P, _SZ, _P, _P]
+_lib.hf_histogram.restype = ctypes.c_int
+_lib.hf_build_codebook.argtypes = [_P, ctypes.POINTER(hf_codebook), _P, _SZ, _P, _P]
+_lib.hf_build_codebook.restype = ctypes.c_int
+_lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _P, _U64, _P, _P,
+                           _SZ, _P, _P]
+_lib.hf_encode.restype = ctypes.c_int
+_lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
+                                 _SZ, _P, _P]
+_lib.hf_decode_check.restype = ctypes.c_int
+
+
+class HFError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {hf_status_string(code)} ({code})")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def hf_status_string(code: int) -> str:
+    return _lib.hf_status_string(code).decode()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != HF_OK:
+        raise HFError(rc, where)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _sym_bytes(sym: torch.Tensor) -> int:
+    if sym.element_size() not in (1, 2) or sym.is_floating_point():
+        raise TypeError(f"symbols must be 8- or 16-bit integers, got {sym.dtype}")
+    if not sym.is_contiguous():
+        raise ValueError("symbols must be contiguous")
+    return sym.element_size()
+
+
+def hf_workspace_bytes(n: int, alphabet: int, chunk_symbols: int = 4096) -> int:
+    return int(_lib.hf_workspace_bytes(n, alphabet, chunk_symbols))
+
+
+def hf_bound_words(n: int, alphabet: int) -> int:
+    return int(_lib.hf_bound_words(n, alphabet))
+
+
+def hf_reduction_factor(beta: float) -> int:
+    return int(_lib.hf_reduction_factor(beta))
+
+
+def hf_time_next_main_kernel(before: torch.cuda.Event | None, after: torch.cuda.Event | None) -> None:
+    """Arm the one-shot timer around the next call's main kernel (this thread)."""
+    b = ctypes.c_void_p(before.cuda_event) if before is not None else ctypes.c_void_p(0)
+    a = ctypes.c_void_p(after.cuda_event) if after is not None else ctypes.c_void_p(0)
+    _check(_lib.hf_time_next_main_kernel(b, a), "hf_time_next_main_kernel")
+
+
+def new_status(device=None) -> torch.Tensor:
+    return torch.zeros(1, dtype=torch.int32, device=device or "cuda")
+
+
+def new_workspace(n: int, alphabet: int, chunk_symbols: int = 4096, device=None) -> torch.Tensor:
+    nbytes = hf_workspace_bytes(n, alphabet, chunk_symbols)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def read_status(status: torch.Tensor) -> int:
+    """Synchronizes with the stream and returns the device status word."""
+    return int(status.item())
+
+
+def raise_on_status(status: torch.Tensor, where: str = "device") -> None:
+    code = read_status(status)
+    if code != HF_OK:
+        raise HFError(code, where)
+
+
+@dataclass
+class Codebook:
+    """Device arrays of one codebook (see hf_codebook in include/hf.h)."""
+
+    alphabet: int
+    cl: torch.Tensor      # uint8[A]
+    cw: torch.Tensor      # int64[A] (bit pattern of uint64)
+    first: torch.Tensor   # int64[65]
+    entry: torch.Tensor   # int32[65]
+    rev: torch.Tensor     # int32[A]
+    info: torch.Tensor    # int64[4]: m, Lmax, total_bits, min_len
+
+    @staticmethod
+    def empty(alphabet: int, device=None) -> "Codebook":
+        d = device or "cuda"
+        return Codebook(
+            alphabet,
+            torch.zeros(alphabet, dtype=torch.uint8, device=d),
+            torch.zeros(alphabet, dtype=torch.int64, device=d),
+            torch.zeros(MAX_CODELEN + 1, dtype=torch.int64, device=d),
+            torch.zeros(MAX_CODELEN + 1, dtype=torch.int32, device=d),
+            torch.zeros(alphabet, dtype=torch.int32, device=d),
+            torch.zeros(4, dtype=torch.int64, device=d),
+        )
+
+    def struct(self) -> hf_codebook:
+        return hf_codebook(self.alphabet, self.cl.data_ptr(), self.cw.data_ptr(), self.first.data_ptr(),
+                           self.entry.data_ptr(), self.rev.data_ptr(), self.info.data_ptr())
+
+
+def hf_histogram(sym: torch.Tensor, alphabet: int, hist: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None, status: torch.Tensor | None = None) -> torch.Tensor:
+    sb = _sym_bytes(sym)
+    if hist is None:
+        hist = torch.empty(alphabet, dtype=torch.int32, device=sym.device)
+    if status is None:
+        status = new_status(sym.device)
+    _check(_lib.hf_histogram(_ptr(sym), sym.numel(), sb, alphabet, _ptr(hist), _ptr(ws),
+                             0 if ws is None else ws.numel(), _ptr(status), _stream()), "hf_histogram")
+    return hist
+
+
+def hf_build_codebook(hist: torch.Tensor, book: Codebook | None = None, ws: torch.Tensor | None = None,
+                      status: torch.Tensor | None = None) -> Codebook:
+    if book is None:
+        book = Codebook.empty(hist.numel(), hist.device)
+    if status is None:
+        status = new_status(hist.device)
+    s = book.struct()
+    _check(_lib.hf_build_codebook(_ptr(hist), ctypes.byref(s), _ptr(ws), 0 if ws is None else ws.numel(),
+                                  _ptr(status), _stream()), "hf_build_codebook")
+    return book
+
+
+def hf_encode(sym: torch.Tensor, book: Codebook, chunk_symbols: int = 4096, reduce_log2: int = 0,
+              out: torch.Tensor | None = None, offsets: torch.Tensor | None = None,
+              ws: torch.Tensor | None = None, status: torch.Tensor | None = None):
+    """Returns (out words as int32 tensor, chunk bit offsets as int64 tensor)."""
+    sb = _sym_bytes(sym)
+    n = sym.numel()
+    nch = (n + chunk_symbols - 1) // chunk_symbols
+    if out is None:
+        out = torch.empty(max(1, hf_bound_words(n, book.alphabet)), dtype=torch.int32, device=sym.device)
+    if offsets is None:
+        offsets = torch.empty(nch + 1, dtype=torch.int64, device=sym.device)
+    if ws is None:
+        ws = new_workspace(n, book.alphabet, chunk_symbols, sym.device)
+    if status is None:
+        status = new_status(sym.device)
+    s = book.struct()
+    _check(_lib.hf_encode(_ptr(sym), n, sb, ctypes.byref(s), chunk_symbols, reduce_log2, _ptr(out),
+                          out.numel(), _ptr(offsets), _ptr(ws), ws.numel(), _ptr(status), _stream()),
+           "hf_encode")
+    return out, offsets
+
+
+def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor, chunk_symbols: int,
+                    book: Codebook, result: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None) -> torch.Tensor:
+    """Returns int64[2] = (mismatches, first mismatching index or n)."""
+    sb = _sym_bytes(sym)
+    if result is None:
+        result = torch.empty(2, dtype=torch.int64, device=sym.device)
+    if status is None:
+        status = new_status(sym.device)
+    s = book.struct()
+    _check(_lib.hf_decode_check(_ptr(out), _ptr(offsets), sym.numel(), sb, chunk_symbols, ctypes.byref(s),
+                                _ptr(sym), _ptr(result), _ptr(ws), 0 if ws is None else ws.numel(),
+                                _ptr(status), _stream()), "hf_decode_check")
+    return result
+
+
+class Encoder:
+    """Pre-allocated buffers for repeated hist -> codebook -> encode passes
+    over streams of at most `max_n` symbols (nothing is allocated per call)."""
+
+    def __init__(self, max_n: int, alphabet: int, chunk_symbols: int = 4096, reduce_log2: int = 0,
+                 device="cuda"):
+        self.max_n = max_n
+        self.alphabet = alphabet
+        self.chunk = chunk_symbols
+        self.r = reduce_log2
+        self.hist = torch.empty(alphabet, dtype=torch.int32, device=device)
+        self.book = Codebook.empty(alphabet, device)
+        self.ws = new_workspace(max_n, alphabet, chunk_symbols, device)
+        self.status = new_status(device)
+        self.out = torch.empty(max(1, hf_bound_words(max_n, alphabet)), dtype=torch.int32, device=device)
+        self.offsets = torch.empty((max_n + chunk_symbols - 1) // chunk_symbols + 1, dtype=torch.int64,
+                                   device=device)
+
+    def run(self, sym: torch.Tensor, timers=None):
+        """One pass of the whole path.  `timers` (optional) maps 'hist',
+        'codebook', 'encode' to (before, after) torch.cuda.Event pairs
+        recorded around each stage's main kernel."""
+        n = sym.numel()
+        assert n <= self.max_n
+        nch = (n + self.chunk - 1) // self.chunk
+        if timers and "hist" in timers:
+            hf_time_next_main_kernel(*timers["hist"])
+        hf_histogram(sym, self.alphabet, self.hist, self.ws, self.status)
+        if timers and "codebook" in timers:
+            hf_time_next_main_kernel(*timers["codebook"])
+        hf_build_codebook(self.hist, self.book, self.ws, self.status)
+        if timers and "encode" in timers:
+            hf_time_next_main_kernel(*timers["encode"])
+        hf_encode(sym, self.book, self.chunk, self.r, self.out, self.offsets[: nch + 1], self.ws, self.status)
+        return self.out, self.offsets[: nch + 1]

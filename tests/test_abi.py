@@ -1,0 +1,85 @@
+"""Host-side checks of libhf that need no GPU: the library loads, exports
+every entry point include/hf.h declares, rejects bad arguments before any
+device work, and implements the paper's reduction-factor rule."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hf.h")
+LIB = os.path.join(ROOT, "paper_2010_10039_amd", "libhf.so")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hf_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libhf.so is not built (python -m paper_2010_10039_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ("hf_histogram", "hf_build_codebook", "hf_encode", "hf_decode_check",
+                 "hf_workspace_bytes", "hf_bound_words"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_bound_words(lib):
+    lib.hf_bound_words.restype = ctypes.c_uint64
+    lib.hf_bound_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    # ceil(log2 A) + 1 bits per symbol, plus one word
+    assert lib.hf_bound_words(1 << 20, 1024) == ((1 << 20) * 11 + 31) // 32 + 1
+    assert lib.hf_bound_words(100, 256) == (100 * 9 + 31) // 32 + 1
+    assert lib.hf_bound_words(7, 1) == (7 + 31) // 32 + 1
+
+
+def test_workspace_grows_with_n_and_large_alphabets(lib):
+    f = lib.hf_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+    assert f(1 << 27, 1024, 4096) > f(1 << 20, 1024, 4096) >= 256
+    assert f(1000, 65536, 4096) > f(1000, 1024, 4096)
+
+
+def test_reduction_factor_rule_matches_table4(lib):
+    """floor(log2 beta) + r + 1 = log2 32 (Sec. 4.3).  Table 4 lists the
+    average bitwidth and the reduction factor used per dataset; the rule
+    reproduces it for the five byte datasets (Nyx-Quant's r = 3 was chosen
+    empirically over the rule's 4, Sec. 4.3 / Table 3)."""
+    lib.hf_reduction_factor.restype = ctypes.c_uint32
+    lib.hf_reduction_factor.argtypes = [ctypes.c_double]
+    table4 = [(5.1639, 2), (5.2124, 2), (4.0165, 2), (2.7307, 3), (4.1428, 2)]
+    for beta, r in table4:
+        assert lib.hf_reduction_factor(beta) == r
+    assert lib.hf_reduction_factor(1.0272) == 4
+    assert lib.hf_reduction_factor(40.0) == 1  # clamped
+
+
+def test_host_argument_checks_return_before_device_work(lib):
+    P = ctypes.c_void_p
+    lib.hf_histogram.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P,
+                                 ctypes.c_size_t, P, P]
+    dummy = P(0x1000)
+    # sym_bytes 3, alphabet 0, uint8 with alphabet > 256, n >= 2^32
+    assert lib.hf_histogram(dummy, 10, 3, 16, dummy, None, 0, dummy, None) == 1
+    assert lib.hf_histogram(dummy, 10, 2, 0, dummy, None, 0, dummy, None) == 1
+    assert lib.hf_histogram(dummy, 10, 1, 300, dummy, None, 0, dummy, None) == 1
+    assert lib.hf_histogram(dummy, 1 << 32, 2, 16, dummy, None, 0, dummy, None) == 1
+    # misaligned 16-bit symbols
+    assert lib.hf_histogram(P(0x1001), 10, 2, 16, dummy, None, 0, dummy, None) == 1
+    lib.hf_status_string.restype = ctypes.c_char_p
+    assert b"argument" in lib.hf_status_string(1)

@@ -1,0 +1,294 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+All of this is integer work, so every comparison is bit-exact: histogram
+bins, code lengths, codewords, First/Entry/rev tables, info, every output
+word and every chunk offset.  Inputs are seeded; sizes span many tiles with
+ragged tails; the full-size workloads are compared whole (the oracle
+finishes them in seconds)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_10039_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2010_10039_amd import hf  # noqa: E402  (raises if libhf.so is missing)
+
+SENTINEL = 0x5A5A5A5A
+
+
+def _dev(x: np.ndarray) -> torch.Tensor:
+    if x.dtype == np.uint16:
+        return torch.from_numpy(x.view(np.int16)).cuda()
+    return torch.from_numpy(x).cuda()
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def gpu_hist(x: np.ndarray, A: int, offset: int = 0):
+    """Histogram of x on the GPU; `offset` > 0 places x at a misaligned
+    address inside a larger buffer."""
+    buf = np.zeros(x.size + offset, dtype=x.dtype)
+    buf[offset:] = x
+    d = _dev(buf)[offset:]
+    status = hf.new_status()
+    h = hf.hf_histogram(d, A, status=status)
+    assert hf.read_status(status) == 0
+    return h.cpu().numpy().view(np.uint32)
+
+
+def gpu_book(h: np.ndarray):
+    A = h.size
+    hd = torch.from_numpy(h.view(np.int32)).cuda()
+    ws = hf.new_workspace(1, A)
+    status = hf.new_status()
+    book = hf.hf_build_codebook(hd, ws=ws, status=status)
+    code = hf.read_status(status)
+    return book, code
+
+
+def assert_book_equal(book, ref: oracle.Codebook):
+    m = ref.m
+    assert np.array_equal(_u64(book.info), ref.info)
+    assert np.array_equal(book.cl.cpu().numpy(), ref.cl)
+    assert np.array_equal(_u64(book.cw), ref.cw)
+    assert np.array_equal(_u64(book.first), ref.first)
+    assert np.array_equal(_u32(book.entry), ref.entry)
+    assert np.array_equal(_u32(book.rev)[:m], ref.rev[:m])
+
+
+def gpu_encode(x: np.ndarray, book, chunk: int, r: int = 0, cap_words: int | None = None):
+    d = _dev(x)
+    n = x.size
+    cap = cap_words if cap_words is not None else hf.hf_bound_words(n, book.alphabet)
+    out = torch.full((cap + 64,), SENTINEL, dtype=torch.int32, device="cuda")
+    nch = (n + chunk - 1) // chunk
+    offsets = torch.full((nch + 1,), -1, dtype=torch.int64, device="cuda")
+    ws = hf.new_workspace(n, book.alphabet, chunk)
+    status = hf.new_status()
+    hf.hf_encode(d, book, chunk, r, out[:cap], offsets, ws, status)
+    code = hf.read_status(status)
+    return _u32(out), _u64(offsets), code
+
+
+def check_pipeline(x: np.ndarray, A: int, chunk: int, r: int = 0):
+    ref_h = oracle.histogram(x, A)
+    h = gpu_hist(x, A)
+    assert np.array_equal(h, ref_h)
+    ref = oracle.codebook(ref_h)
+    book, code = gpu_book(h)
+    assert code == 0
+    assert_book_equal(book, ref)
+    words, offs, code = gpu_encode(x, book, chunk, r)
+    assert code == 0
+    ref_words, ref_offs, tb = oracle.encode(x, ref, chunk)
+    nw = (tb + 31) // 32
+    assert np.array_equal(offs, ref_offs)
+    assert np.array_equal(words[:nw], ref_words[:nw])
+    assert np.all(words[nw:] == SENTINEL)  # nothing written past the stream
+    return book, words, offs, tb
+
+
+# ---------------------------------------------------------------------------
+# histogram
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,A,dtype,offset", [
+    (1, 16, np.uint16, 0), (7, 256, np.uint8, 3), (1000, 1024, np.uint16, 1),
+    (1_000_003, 1024, np.uint16, 0), (2_000_001, 256, np.uint8, 5),
+    (300_001, 65536, np.uint16, 0), (300_001, 20000, np.uint16, 2), (0, 64, np.uint16, 0)])
+def test_histogram_parity(n, A, dtype, offset):
+    rng = np.random.default_rng(n + A)
+    x = np.clip(np.rint(rng.normal(A / 2, max(1.0, A / 16), size=n)), 0, A - 1).astype(dtype)
+    assert np.array_equal(gpu_hist(x, A, offset), oracle.histogram(x, A))
+
+
+def test_histogram_peaked_single_bin():
+    x = np.full(3_000_017, 511, dtype=np.uint16)
+    x[::1000] = 3
+    assert np.array_equal(gpu_hist(x, 1024), oracle.histogram(x, 1024))
+
+
+def test_histogram_flags_out_of_range_symbol():
+    x = np.zeros(100_000, dtype=np.uint16)
+    x[77_777] = 1024
+    d = _dev(x)
+    status = hf.new_status()
+    hf.hf_histogram(d, 1024, status=status)
+    assert hf.read_status(status) == hf.HF_ERR_SYMBOL
+
+
+# ---------------------------------------------------------------------------
+# codebook
+# ---------------------------------------------------------------------------
+def _fib(m):
+    f = [1, 1]
+    while len(f) < m:
+        f.append(f[-1] + f[-2])
+    return f[:m]
+
+
+def _hist_cases():
+    rng = np.random.default_rng(123)
+    cases = {}
+    cases["empty"] = np.zeros(64, np.uint32)
+    h = np.zeros(64, np.uint32); h[17] = 5; cases["one"] = h
+    h = np.zeros(64, np.uint32); h[3] = 5; h[60] = 1; cases["two"] = h
+    cases["uniform1024"] = np.full(1024, 9, np.uint32)
+    cases["ties"] = rng.choice(np.array([0, 1, 1, 2, 3, 3, 8]), size=1024).astype(np.uint32)
+    cases["gauss"] = oracle.histogram(W.gaussian_codes(n=1 << 16, seed=5), 1024)
+    cases["zipf256"] = oracle.histogram(W.zipf_bytes(n=1 << 18, seed=6), 256)
+    h = np.zeros(1024, np.uint32); h[100:140] = _fib(40); cases["fib40_codes_over_32_bits"] = h
+    h = np.zeros(256, np.uint32); h[:46] = _fib(46); cases["fib46"] = h
+    cases["m4096"] = (rng.integers(1, 1000, size=4096)).astype(np.uint32)
+    h = rng.integers(1, 1000, size=4097).astype(np.uint32); cases["m4097_global"] = h
+    cases["normal65536"] = W.skewed_histogram(65536, 3_000_000, seed=7)
+    cases["uniform65536"] = W.skewed_histogram(65536, 65536 * 3, kind="uniform")
+    h = rng.integers(0, 3, size=8192).astype(np.uint32) * rng.integers(1, 1 << 20, size=8192).astype(np.uint32)
+    cases["sparse8192"] = h
+    return cases
+
+
+HISTS = _hist_cases()
+
+
+@pytest.mark.parametrize("name", sorted(HISTS))
+def test_codebook_parity(name):
+    h = HISTS[name]
+    ref = oracle.codebook(h)
+    book, code = gpu_book(h)
+    assert code == 0
+    assert_book_equal(book, ref)
+
+
+# ---------------------------------------------------------------------------
+# encoding
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 255, 256, 4095, 4097, 70_001, 1 << 20])
+def test_encode_small_and_ragged(n):
+    x = W.gaussian_codes(n=n, seed=n)
+    check_pipeline(x, 1024, 256)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6])
+def test_encode_independent_of_r(r):
+    x = W.gaussian_codes(n=300_007, sigma=20.0, seed=3)
+    check_pipeline(x, 1024, 1024, r)
+
+
+@pytest.mark.parametrize("chunk", [256, 1024, 4096, 65536])
+def test_encode_independent_of_chunk(chunk):
+    x = W.zipf_bytes(n=1_000_003, seed=2)
+    check_pipeline(x, 256, chunk)
+
+
+def test_encode_single_symbol_stream():
+    x = np.full(100_000, 7, dtype=np.uint16)
+    book, words, offs, tb = check_pipeline(x, 16, 4096)
+    assert tb == x.size
+
+
+def test_encode_long_codes_wide_path():
+    """Fibonacci weights give 39-bit codes: the lane accumulator path for
+    codes longer than 32 bits."""
+    f = _fib(40)
+    h = np.zeros(1024, np.uint32)
+    h[100:140] = f
+    rng = np.random.default_rng(9)
+    x = rng.choice(np.arange(100, 140), size=50_000, p=np.array(f, float) / sum(f)).astype(np.uint16)
+    x[:40] = np.arange(100, 140)  # every code appears
+    ref_h = oracle.histogram(x, 1024)
+    ref = oracle.codebook(ref_h)
+    book, code = gpu_book(ref_h)
+    assert code == 0
+    assert_book_equal(book, ref)
+    words, offs, code = gpu_encode(x, book, 1024)
+    assert code == 0
+    rw, ro, tb = oracle.encode(x, ref, 1024)
+    assert np.array_equal(offs, ro) and np.array_equal(words[: rw.size], rw)
+
+
+def test_encode_large_alphabet_global_table():
+    x = np.clip(np.rint(np.random.default_rng(4).normal(30000, 3000, size=500_001)), 0, 65535).astype(np.uint16)
+    check_pipeline(x, 65536, 4096)
+
+
+def test_encode_capacity_error_writes_nothing_past_capacity():
+    x = W.gaussian_codes(n=200_000, seed=1)
+    ref = oracle.codebook(oracle.histogram(x, 1024))
+    book, _ = gpu_book(oracle.histogram(x, 1024))
+    cap = ref.total_bits // 64  # half of what is needed
+    words, offs, code = gpu_encode(x, book, 4096, cap_words=cap)
+    assert code == hf.HF_ERR_CAPACITY
+    assert np.all(words[cap:] == SENTINEL)
+
+
+def test_encode_flags_symbol_without_code():
+    x = W.gaussian_codes(n=50_000, seed=1)
+    book, _ = gpu_book(oracle.histogram(x, 1024))
+    y = x.copy()
+    y[12345] = 1000  # no code in this book
+    _, _, code = gpu_encode(y, book, 4096)
+    assert code == hf.HF_ERR_SYMBOL
+
+
+def test_encode_deterministic_across_runs():
+    x = W.zipf_bytes(n=3_000_000, seed=11)
+    book, _ = gpu_book(oracle.histogram(x, 256))
+    a = gpu_encode(x, book, 4096)
+    for _ in range(3):
+        b = gpu_encode(x, book, 4096)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# decode check
+# ---------------------------------------------------------------------------
+def test_decode_check_accepts_and_rejects():
+    x = W.gaussian_codes(n=500_000, sigma=10.0, seed=8)
+    d = _dev(x)
+    enc = hf.Encoder(x.size, 1024, 4096)
+    out, offs = enc.run(d)
+    res = hf.hf_decode_check(out, offs, d, 4096, enc.book)
+    assert res.cpu().tolist() == [0, x.size]
+    assert hf.read_status(enc.status) == 0
+    bad = out.clone()
+    bad[1000] ^= 1 << 7
+    status = hf.new_status()
+    res = hf.hf_decode_check(bad, offs, d, 4096, enc.book, status=status)
+    r = res.cpu().tolist()
+    assert r[0] > 0 and r[1] < x.size
+    assert hf.read_status(status) == hf.HF_ERR_MISMATCH
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, whole-output comparison
+# ---------------------------------------------------------------------------
+def _full(x, A, chunk):
+    book, words, offs, tb = check_pipeline(x, A, chunk)
+    d = _dev(x)
+    res = hf.hf_decode_check(torch.from_numpy(words.view(np.int32)).cuda(),
+                             torch.from_numpy(offs.view(np.int64)).cuda(), d, chunk, book)
+    assert res.cpu().tolist() == [0, x.size]
+
+
+def test_full_gaussian_1M_u16():
+    _full(W.make("gaussian_1M_u16_A1024"), 1024, 4096)
+
+
+def test_full_lorenzo_512cube_u16():
+    _full(W.make("lorenzo3d_512cube_u16_A1024"), 1024, 4096)
+
+
+def test_full_zipf_100M_u8():
+    _full(W.make("zipf_100M_u8_A256"), 256, 4096)
