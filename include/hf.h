@@ -96,15 +96,29 @@ uint32_t hf_reduction_factor(double beta);
 const char* hf_status_string(uint32_t code);
 
 /*
+ * Slabs: the stream is cut into S slabs of whole 4096-symbol blocks, slab g
+ * covering blocks [floor(g*nb/S), floor((g+1)*nb/S)) of nb = ceil(n/4096).
+ * hf_slab_count() returns the S that keeps one encoder workgroup per slab
+ * resident on this device (0 when per-slab counts are not worth keeping:
+ * alphabets above 4096).  Per-slab counts let hf_encode place every slab's
+ * bits without reading the input a second time.  Any slab count passed to
+ * hf_histogram or hf_encode must satisfy 1 <= S <= min(nb, 16384).
+ */
+uint32_t hf_slab_count(uint64_t n, uint32_t alphabet);
+
+/*
  * Stage 1, histogramming (Sec. 4.1): d_hist[s] = number of i < n with
  * d_sym[i] == s, for s < alphabet.  d_hist (uint32[alphabet]) is
- * overwritten.  Symbols >= alphabet are not counted and raise
- * HF_ERR_SYMBOL in *d_status.  Per-workgroup histograms are kept in LDS
- * with several interleaved replicas and merged into d_hist with atomics.
+ * overwritten.  If d_slab_hist is not NULL (then nslabs >= 1, alphabet <=
+ * 4096), d_slab_hist[g * alphabet + s] (uint32[nslabs * alphabet]) receives
+ * the count of s inside slab g.  Symbols >= alphabet are not counted and
+ * raise HF_ERR_SYMBOL in *d_status.  Each workgroup keeps interleaved
+ * replicated sub-histograms in LDS and merges them into d_hist with one
+ * atomic per non-zero bin.
  */
 hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
-                       uint32_t* d_hist, void* d_ws, size_t ws_bytes, uint32_t* d_status,
-                       void* stream);
+                       uint32_t* d_hist, uint32_t nslabs, uint32_t* d_slab_hist, void* d_ws,
+                       size_t ws_bytes, uint32_t* d_status, void* stream);
 
 /*
  * Stages 2 and 3, codebook construction and canonization (Sec. 4.2,
@@ -134,15 +148,20 @@ hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, voi
  *                  merges 2^r consecutive codewords in registers before the
  *                  workgroup-wide shuffle-merge; 1..6, or 0 for the library
  *                  default.  The output does not depend on it.
- * The result is bit-identical for every chunk_symbols and reduce_log2.
- * Raises HF_ERR_SYMBOL for a symbol >= alphabet or with cl == 0, and
- * HF_ERR_CAPACITY when total_bits > 32 * out_capacity_words (nothing is
- * written at or past d_out[out_capacity_words]).
+ *   nslabs, d_slab_hist: the slab partition and per-slab counts written by
+ *                  hf_histogram for these same symbols, or d_slab_hist = NULL
+ *                  (then nslabs = 0 picks hf_slab_count or a default, and
+ *                  one extra pass over the input counts bits per slab).
+ * The result is bit-identical for every chunk_symbols, reduce_log2 and
+ * slab partition.  Raises HF_ERR_SYMBOL for a symbol >= alphabet or with
+ * cl == 0, and HF_ERR_CAPACITY when total_bits > 32 * out_capacity_words
+ * (nothing is written at or past d_out[out_capacity_words]).
  */
 hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
-                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t* d_out,
-                    uint64_t out_capacity_words, uint64_t* d_chunk_bit_offsets, void* d_ws,
-                    size_t ws_bytes, uint32_t* d_status, void* stream);
+                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t nslabs,
+                    const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,
+                    uint64_t* d_chunk_bit_offsets, void* d_ws, size_t ws_bytes,
+                    uint32_t* d_status, void* stream);
 
 /*
  * Checker: decodes every chunk of d_out from its offset with the canonical

@@ -59,20 +59,33 @@ uint32_t effective_r(uint32_t r) { return r == 0 ? (uint32_t)hf::kEncDefaultR : 
 
 hf_status launch_result(hipError_t e) { return e == hipSuccess ? HF_OK : HF_ERR_LAUNCH; }
 
+uint64_t blocks_of(uint64_t n) { return (n + hf::kSlabBlock - 1) / hf::kSlabBlock; }
+
+// One encoder workgroup per slab, as many slabs as workgroups fit at once.
+uint32_t default_slabs(uint64_t n, uint32_t alphabet, uint32_t sym_bytes) {
+  const uint64_t nb = blocks_of(n);
+  const uint64_t cap = (uint64_t)num_cus() * (uint64_t)hf::encode_blocks_per_cu(alphabet, sym_bytes);
+  uint64_t s = nb < cap ? nb : cap;
+  if (s > hf::kMaxSlabs) s = hf::kMaxSlabs;
+  return (uint32_t)(s > 0 ? s : 1);
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t hf_workspace_bytes(uint64_t n, uint32_t alphabet, uint32_t chunk_symbols) {
   (void)chunk_symbols;
-  size_t enc = 0;
-  for (uint32_t r = hf::kEncMinR; r <= (uint32_t)hf::kEncMaxR; ++r) {
-    const size_t b = hf::encode_workspace_bytes(n, r);
-    if (b > enc) enc = b;
-  }
+  const uint64_t nblocks = (n + hf::kSlabBlock - 1) / hf::kSlabBlock;
+  const size_t enc = hf::encode_workspace_bytes((uint32_t)(nblocks > 0 ? nblocks : 1));
   const size_t cb = hf::codebook_workspace_bytes(alphabet);
   const size_t need = enc > cb ? enc : cb;
   return need < 256 ? 256 : need;
+}
+
+uint32_t hf_slab_count(uint64_t n, uint32_t alphabet) {
+  if (alphabet == 0 || alphabet > hf::kSlabHistMaxAlphabet || n == 0) return 0;
+  return default_slabs(n, alphabet, 2);
 }
 
 uint64_t hf_bound_words(uint64_t n, uint32_t alphabet) {
@@ -111,16 +124,19 @@ hf_status hf_time_next_main_kernel(void* before_event, void* after_event) {
 }
 
 hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
-                       uint32_t* d_hist, void* d_ws, size_t ws_bytes, uint32_t* d_status,
-                       void* stream) {
+                       uint32_t* d_hist, uint32_t nslabs, uint32_t* d_slab_hist, void* d_ws,
+                       size_t ws_bytes, uint32_t* d_status, void* stream) {
   (void)d_ws;
   (void)ws_bytes;
   const KernelTimer timer = take_timer();
   if (!valid_symbols(sym_bytes, alphabet, n) || !d_hist || !d_status || (n > 0 && !d_sym))
     return HF_ERR_ARG;
   if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
-  return launch_result(hf::launch_histogram(d_sym, n, sym_bytes, alphabet, d_hist, d_status, num_cus(),
-                                            (hipStream_t)stream, timer));
+  if (d_slab_hist && (nslabs == 0 || nslabs > blocks_of(n) || nslabs > hf::kMaxSlabs ||
+                      alphabet > hf::kSlabHistMaxAlphabet))
+    return HF_ERR_ARG;
+  return launch_result(hf::launch_histogram(d_sym, n, sym_bytes, alphabet, d_hist, nslabs, d_slab_hist,
+                                            d_status, num_cus(), (hipStream_t)stream, timer));
 }
 
 hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
@@ -133,21 +149,25 @@ hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, voi
 }
 
 hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
-                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t* d_out,
-                    uint64_t out_capacity_words, uint64_t* d_chunk_bit_offsets, void* d_ws,
-                    size_t ws_bytes, uint32_t* d_status, void* stream) {
+                    uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t nslabs,
+                    const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,
+                    uint64_t* d_chunk_bit_offsets, void* d_ws, size_t ws_bytes,
+                    uint32_t* d_status, void* stream) {
   const KernelTimer timer = take_timer();
   if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
       !d_chunk_bit_offsets || !d_status || (n > 0 && (!d_sym || !d_out)))
     return HF_ERR_ARG;
   if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
   if (reduce_log2 > (uint32_t)hf::kEncMaxR) return HF_ERR_ARG;
+  if (nslabs > blocks_of(n) || nslabs > hf::kMaxSlabs) return HF_ERR_ARG;
+  if (d_slab_hist && (nslabs == 0 || book->alphabet > hf::kSlabHistMaxAlphabet)) return HF_ERR_ARG;
+  if (n > 0 && nslabs == 0) nslabs = default_slabs(n, book->alphabet, sym_bytes);
   const uint32_t r = effective_r(reduce_log2);
-  const size_t need = hf::encode_workspace_bytes(n, r);
-  if (n > 0 && (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255))) return HF_ERR_WORKSPACE;
-  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, d_out,
-                                         out_capacity_words, d_chunk_bit_offsets, d_ws, d_status,
-                                         num_cus(), (hipStream_t)stream, timer));
+  if (n > 0 && (!d_ws || ws_bytes < hf::encode_workspace_bytes(nslabs) || ((uintptr_t)d_ws & 255)))
+    return HF_ERR_WORKSPACE;
+  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, nslabs,
+                                         d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,
+                                         d_ws, d_status, (hipStream_t)stream, timer));
 }
 
 hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets, uint64_t n,

@@ -2,33 +2,33 @@
 // paper: reduce-merge, shuffle-merge, blockwise code-length prefix sum and
 // the coalescing copy of Table 1).
 //
-// The paper encodes a chunk of 2^M symbols with M merge rounds: r rounds of
-// reduce-merge inside a thread, then s = M - r rounds of shuffle-merge in
-// which right groups of 32-bit words are appended to left groups; chunks are
-// then stitched with a prefix sum of their lengths and an optional gathering
-// copy.  Here one workgroup of 256 lanes encodes a tile of 256 * 2^r
-// symbols:
-//  - reduce-merge: each lane looks up 2^r consecutive symbols in an LDS
-//    codebook (packed cw << 5 | cl when every code has <= 27 bits) and
-//    concatenates them in a 64-bit register, so codes up to 64 bits need no
-//    side channel (the paper filters merged words over 32 bits out);
-//  - shuffle-merge: the s pairwise append rounds collapse into one
-//    workgroup exclusive scan of the lane bit counts, after which every lane
-//    ORs its words into an LDS tile buffer at its bit offset (no contention
-//    beyond the one word shared with each neighbour);
-//  - tile offsets: single-pass decoupled look-back (Merrill & Garland) over
-//    per-tile records {flag, aggregate | inclusive prefix} instead of a
-//    separate prefix-sum kernel;
-//  - gathering: the tile buffer, assembled at bit alignment 0, is written to
-//    its final bit position in HBM with a funnel shift and coalesced stores.
-//    The word shared with the previous tile belongs to this tile, which
-//    completes it from the previous tile's published last 32 bits, so every
-//    output word is stored exactly once with a plain store.
-// Chunk offsets (the paper's per-chunk metadata) are the bit positions of
-// the lanes that start a chunk, so the stream does not depend on the chunk
-// size or on r.  Tiles are handed out by an atomic ticket so a tile only
-// waits on tiles already taken by running workgroups.
+// The paper encodes each chunk of 2^M symbols with M merge rounds (r rounds
+// of reduce-merge inside a thread, then s = M - r rounds of shuffle-merge
+// that append right groups of 32-bit words to left groups), then needs a
+// prefix sum of the chunk lengths and an optional gathering copy to make
+// the stream dense.  Here the stream is cut into slabs (whole 4096-symbol
+// blocks, one workgroup each), and:
+//  - slab offsets: a slab's bit total is sum_s count_g[s] * cl[s], taken from
+//    the per-slab counts the histogram pass already produced (or, without
+//    them, from one counting pass); each workgroup adds its predecessors'
+//    totals.  No flags, no waiting between workgroups, no cleared state;
+//  - reduce-merge: each lane looks up 2^r consecutive symbols (packed
+//    cw << 5 | cl table in LDS when codes fit 27 bits) and concatenates their
+//    codes in a 64-bit register, so codes up to 64 bits need no side
+//    channel (the paper filters merged words over 32 bits out);
+//  - shuffle-merge: the s pairwise append rounds become one workgroup scan of
+//    lane bit counts, after which each lane ORs its words into an LDS tile
+//    buffer at its bit offset;
+//  - gathering: the tile buffer (bit alignment 0) is stored to its final
+//    position with a funnel shift and coalesced 32-bit stores.  A word shared
+//    with the previous tile belongs to the later tile, which completes it
+//    from the earlier tile's last 32 bits (kept in LDS inside a slab and
+//    computed by the prepass across slabs), so every output word is stored
+//    once with a plain store.
+// Chunk offsets are the bit positions of the lanes that start a chunk, so
+// the stream does not depend on the chunk size, on r or on the slabs.
 #include <algorithm>
+#include <mutex>
 
 #include "hf_device.h"
 #include "hf_kernels.h"
@@ -37,284 +37,399 @@ namespace hf {
 
 namespace {
 
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
-constexpr uint64_t kTailValid = 1ull << 32;
-// Upper bound on polls of another tile's record (~0.5 s of sleeping polls);
-// reaching it means a bug, reported as HF_ERR_INTERNAL instead of a hang.
-constexpr uint32_t kSpinLimit = 1u << 22;
+// The LDS tile buffer holds codes of up to this many bits per symbol.
+constexpr uint32_t kLdsBufMaxLen = 32;
+constexpr uint32_t kTableMaxAlphabet = 8192;
+constexpr int kPreThreads = 256;
+constexpr int kPreWaves = kPreThreads / kWave;
 
-struct EncShared {
-  uint32_t wtot[kEncWaves];
-  uint32_t tile[2];
-  uint64_t G;
-  uint32_t pred_tail;
+// Encoding modes, chosen per launch from the codebook's longest code:
+//   kModeTable : codes <= 27 bits, alphabet <= 8192: packed (cw << 5 | cl)
+//                table and tile buffer in LDS;
+//   kModeGlobal: codes <= 32 bits: codebook read from global memory (L2),
+//                tile buffer in LDS;
+//   kModeWide  : longer codes: codebook from global memory and bits ORed
+//                straight into the output words the tile owns.
+constexpr int kModeTable = 0;
+constexpr int kModeGlobal = 1;
+constexpr int kModeWide = 2;
+
+struct SlabArgs {
+  const void* sym;
+  uint64_t n;
+  uint64_t nblocks;
+  uint32_t nslabs;
+  uint32_t A;
+  const uint8_t* cl;
+  const uint64_t* cw;
+  const uint32_t* slab_hist;  // [nslabs * A] or null
+  uint64_t* bits;             // [nslabs] bit total per slab
+  uint32_t* tails;            // [nslabs] last 32 content bits per slab
+  uint32_t* status;
 };
 
-template <int NS, int SB>
-__device__ __forceinline__ void load_symbols(const void* __restrict__ sym, uint64_t s0, uint64_t n,
-                                             bool vec_ok, uint32_t (&v)[NS], uint32_t& nvalid) {
-  if (s0 + NS <= n) {
-    nvalid = NS;
-    constexpr int kBytes = NS * SB;
-    const char* p = (const char*)sym + s0 * SB;
-    if constexpr (kBytes >= 4) {
-      if (vec_ok) {
-        constexpr int kWords = kBytes / 4;
-        uint32_t w[kWords];
-        if constexpr (kBytes >= 16) {
-#pragma unroll
-          for (int k = 0; k < kBytes / 16; ++k) {
-            const uint4 q = ((const uint4*)p)[k];
-            w[4 * k + 0] = q.x;
-            w[4 * k + 1] = q.y;
-            w[4 * k + 2] = q.z;
-            w[4 * k + 3] = q.w;
-          }
-        } else if constexpr (kBytes == 8) {
-          const uint2 q = *(const uint2*)p;
-          w[0] = q.x;
-          w[1] = q.y;
-        } else {
-          w[0] = *(const uint32_t*)p;
-        }
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          if (SB == 1) v[i] = (w[i / 4] >> (8 * (i % 4))) & 0xFFu;
-          else v[i] = (w[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
-        }
-        return;
-      }
-    }
-    {
-#pragma unroll
-      for (int i = 0; i < NS; ++i)
-        v[i] = (SB == 1) ? (uint32_t)((const uint8_t*)sym)[s0 + i] : (uint32_t)((const uint16_t*)sym)[s0 + i];
-    }
-  } else {
-    nvalid = s0 < n ? (uint32_t)(n - s0) : 0u;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      v[i] = 0;
-      if ((uint32_t)i < nvalid)
-        v[i] = (SB == 1) ? (uint32_t)((const uint8_t*)sym)[s0 + i] : (uint32_t)((const uint16_t*)sym)[s0 + i];
-    }
-  }
+struct EncArgs {
+  const void* sym;
+  uint64_t n;
+  uint64_t nblocks;
+  uint32_t nslabs;
+  uint32_t A;
+  const uint8_t* cl;
+  const uint64_t* cw;
+  const uint64_t* info;
+  const uint64_t* bits;
+  const uint32_t* tails;
+  uint32_t* out;
+  uint64_t cap_words;
+  uint64_t* offsets;
+  uint32_t chunk_log2;
+  uint64_t nchunks;
+  uint32_t* status;
+  uint32_t vec_ok;
+};
+
+template <int SB>
+__device__ __forceinline__ uint32_t sym_at(const void* p, uint64_t i) {
+  return SB == 1 ? (uint32_t)((const uint8_t*)p)[i] : (uint32_t)((const uint16_t*)p)[i];
 }
 
-// Append `len` (<= 32) bits of `code` to the lane accumulator; full 32-bit
-// words go to the tile buffer (the first and last may be shared with the
-// neighbouring lanes, hence the OR).
-__device__ __forceinline__ void push_bits(uint64_t& acc, uint32_t& nb, uint32_t& wi, uint32_t* buf,
-                                          uint32_t code, uint32_t len) {
+template <int NS, int SB>
+struct Raw {
+  static constexpr int kBytes = NS * SB;
+  static constexpr int kWords = (kBytes + 3) / 4;
+  uint32_t w[kWords];
+
+  // Symbols [s0, s0 + NS) clipped to `end`.
+  __device__ __forceinline__ void load(const void* sym, uint64_t s0, uint64_t end, bool vec_ok) {
+    if (s0 + NS <= end && vec_ok && kBytes >= 4) {
+      const char* p = (const char*)sym + s0 * SB;
+      if constexpr (kBytes >= 16) {
+#pragma unroll
+        for (int k = 0; k < kBytes / 16; ++k) {
+          const uint4 q = ((const uint4*)p)[k];
+          w[4 * k + 0] = q.x;
+          w[4 * k + 1] = q.y;
+          w[4 * k + 2] = q.z;
+          w[4 * k + 3] = q.w;
+        }
+      } else if constexpr (kBytes == 8) {
+        const uint2 q = *(const uint2*)p;
+        w[0] = q.x;
+        w[1] = q.y;
+      } else if constexpr (kBytes == 4) {
+        w[0] = *(const uint32_t*)p;
+      }
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) w[k] = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      if (s0 + i < end) w[(i * SB) / 4] |= sym_at<SB>(sym, s0 + i) << (8 * ((i * SB) % 4));
+  }
+
+  __device__ __forceinline__ uint32_t symbol(int i) const {
+    if (SB == 1) return (w[i / 4] >> (8 * (i % 4))) & 0xFFu;
+    return (w[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
+  }
+};
+
+// Append `len` (<= 32) bits of `code` to the lane accumulator; each full
+// 32-bit word is ORed into dst (the first and last may be shared with the
+// neighbouring lanes).  Words at index >= limit are dropped.
+template <typename Dst>
+__device__ __forceinline__ void push_bits(uint64_t& acc, uint32_t& nb, uint64_t& wi, Dst* dst,
+                                          uint64_t limit, uint32_t code, uint32_t len) {
   acc = (len == 32) ? ((acc << 32) | code) : ((acc << len) | code);
   nb += len;
   if (nb >= 32) {
     nb -= 32;
-    atomicOr(&buf[wi++], (uint32_t)(acc >> nb));
+    if (wi < limit) atomicOr(&dst[wi], (uint32_t)(acc >> nb));
+    ++wi;
   }
 }
 
-template <int R, int SB>
-__global__ __launch_bounds__(kEncThreads) void encode_kernel(
-    const void* __restrict__ sym, uint64_t n, uint32_t A, const uint8_t* __restrict__ cl,
-    const uint64_t* __restrict__ cw, const uint64_t* __restrict__ info, uint32_t* __restrict__ out,
-    uint64_t cap_words, uint64_t* __restrict__ offsets, uint32_t chunk_log2, uint64_t nchunks,
-    uint32_t* __restrict__ ticket, uint64_t* __restrict__ lookback, uint64_t* __restrict__ tails,
-    uint32_t ntiles, uint32_t* __restrict__ status, uint32_t table_ok, uint32_t vec_ok) {
+// Bits of code (c, l), which occupies content bits [p, p + l), that fall in
+// [max(B - 32, 0), B), placed as in a last-32-bits record (content bit B - 1
+// at bit 0).
+__device__ __forceinline__ uint32_t tail_part(uint64_t c, uint32_t l, uint32_t p, uint32_t B) {
+  const uint32_t s = B > 32 ? B - 32 : 0u;
+  if (p + l <= s || p >= B) return 0u;
+  const uint32_t lo = p > s ? p : s;
+  const uint32_t hi = p + l < B ? p + l : B;
+  const uint32_t w = hi - lo;
+  const uint64_t seg = (c >> (p + l - hi)) & ((w >= 64) ? ~0ull : ((1ull << w) - 1));
+  return (uint32_t)(seg << (B - hi));
+}
+
+// Last 32 content bits of the symbols [s_lo, s_hi) (right aligned, fewer if
+// the content is shorter), computed by wave 0: lane j codes symbol s_hi-1-j.
+template <int SB>
+__device__ __forceinline__ uint32_t range_tail(const void* sym, uint64_t s_lo, uint64_t s_hi, uint32_t A,
+                                               const uint8_t* cl, const uint64_t* cw) {
+  const uint32_t lane = lane_id();
+  uint32_t l = 0;
+  uint64_t c = 0;
+  if (lane < 32 && s_hi - s_lo > lane) {
+    const uint32_t s = sym_at<SB>(sym, s_hi - 1 - lane);
+    if (s < A) {
+      l = cl[s];
+      c = cw[s];
+    }
+  }
+  // bits already taken by lanes nearer the end
+  const uint32_t off = wave_inclusive_scan(l) - l;
+  uint32_t part = (off < 32) ? (uint32_t)(c << off) : 0u;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) part |= (uint32_t)__shfl_xor(part, d, kWave);
+  return part;
+}
+
+// ---------------------------------------------------------------------------
+// Prepass: bit total and last 32 bits of every slab.
+// ---------------------------------------------------------------------------
+template <int SB>
+__global__ __launch_bounds__(kPreThreads) void slab_bits_kernel(SlabArgs a) {
+  __shared__ uint64_t part[kPreWaves];
+  const uint32_t g = blockIdx.x;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t s_lo = slab_begin(g, a.nblocks, a.nslabs, a.n);
+  const uint64_t s_hi = slab_begin(g + 1, a.nblocks, a.nslabs, a.n);
+  uint64_t bits = 0;
+  bool bad = false;
+  if (a.slab_hist) {
+    const uint32_t* row = a.slab_hist + (uint64_t)g * a.A;
+    for (uint32_t s = tid; s < a.A; s += kPreThreads) bits += (uint64_t)row[s] * a.cl[s];
+  } else {
+    for (uint64_t i = s_lo + tid; i < s_hi; i += kPreThreads) {
+      const uint32_t s = sym_at<SB>(a.sym, i);
+      const uint32_t l = s < a.A ? a.cl[s] : 0u;
+      bad |= l == 0;
+      bits += l;
+    }
+  }
+  bits = wave_sum_u64(bits);
+  if (lane_id() == 0) part[tid / kWave] = bits;
+  uint32_t tail = 0;
+  if (tid < kWave) tail = range_tail<SB>(a.sym, s_lo, s_hi, a.A, a.cl, a.cw);
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kPreWaves; ++w) t += part[w];
+    a.bits[g] = t;
+    a.tails[g] = tail;
+  }
+  if (bad) raise_status(a.status, HF_ERR_SYMBOL);
+}
+
+// ---------------------------------------------------------------------------
+// Encoder: one workgroup per slab.
+// ---------------------------------------------------------------------------
+struct EncShared {
+  uint32_t wtot[kEncWaves];
+  uint64_t red[kEncWaves];
+  uint32_t tail[2];  // last 32 bits of the previous / current tile
+  uint32_t tailw;    // wide mode: current tile's last 32 bits
+};
+
+template <int R, int SB, int MODE>
+__device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* tab, uint32_t* buf,
+                                            EncShared& sh, uint32_t g, uint64_t G) {
   constexpr uint32_t NS = 1u << R;
   constexpr uint32_t T = kEncThreads * NS;
-  extern __shared__ uint32_t lds[];
-  __shared__ EncShared sh;
-
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & (kWave - 1);
-  const uint32_t wave = tid / kWave;
-  const uint32_t lmax = (uint32_t)info[1];
-  const bool packed = table_ok && lmax <= kPackedMaxLen;
-  uint32_t* tab = lds;
-  uint32_t* buf = lds + (packed ? A : 0u);
-  const uint32_t buf_words = packed ? (T * kPackedMaxLen + 31) / 32 + 2 : 2 * T + 2;
+  const uint64_t s_lo = slab_begin(g, a.nblocks, a.nslabs, a.n);
+  const uint64_t s_hi = slab_begin(g + 1, a.nblocks, a.nslabs, a.n);
+  const bool last_slab = g == a.nslabs - 1;
+  const uint32_t ntiles = (uint32_t)((s_hi - s_lo + T - 1) / T);
 
-  if (packed)
-    for (uint32_t s = tid; s < A; s += kEncThreads) {
-      const uint32_t l = cl[s];
-      tab[s] = l ? (((uint32_t)cw[s]) << 5) | l : 0u;
-    }
-  for (uint32_t i = tid; i < buf_words; i += kEncThreads) buf[i] = 0;
-  if (tid == 0) sh.tile[0] = atomicAdd(ticket, 1u);
-  __syncthreads();
+  Raw<NS, SB> raw;
+  raw.load(a.sym, s_lo + (uint64_t)tid * NS, s_hi, a.vec_ok != 0);
+  uint64_t run = 0;  // bits of this slab before the current tile
 
-  for (uint32_t it = 0;; ++it) {
-    const uint32_t tile = sh.tile[it & 1];
-    if (tile >= ntiles) break;
-    if (tid == 0) sh.tile[(it + 1) & 1] = atomicAdd(ticket, 1u);
-    const bool last = tile == ntiles - 1;
-    const uint64_t s0 = (uint64_t)tile * T + (uint64_t)tid * NS;
+  for (uint32_t t = 0; t < ntiles; ++t) {
+    const uint64_t s0 = s_lo + (uint64_t)t * T + (uint64_t)tid * NS;
+    const uint32_t nvalid = s0 >= s_hi ? 0u : (s_hi - s0 >= NS ? NS : (uint32_t)(s_hi - s0));
+    const bool last_tile = t == ntiles - 1;
 
-    // ---- lookup: lane bit count --------------------------------------------
-    uint32_t e[NS];
-    uint32_t nvalid;
-    load_symbols<NS, SB>(sym, s0, n, vec_ok != 0, e, nvalid);
+    // ---- lookup: packed entries (table mode) or symbols; lane bit count ----
+    uint32_t ent[NS];
     uint32_t L = 0;
     bool bad = false;
-    if (packed) {
 #pragma unroll
-      for (uint32_t i = 0; i < NS; ++i) {
-        uint32_t ent = 0;
+    for (uint32_t i = 0; i < NS; ++i) {
+      const uint32_t sv = raw.symbol(i);
+      if (MODE == kModeTable) {
+        ent[i] = 0;
         if (i < nvalid) {
-          ent = e[i] < A ? tab[e[i]] : 0u;
-          bad |= ent == 0;
+          const uint32_t e = sv < a.A ? tab[sv] : 0u;
+          bad |= e == 0;
+          ent[i] = e;
+          L += e & 31;
         }
-        e[i] = ent;
-        L += ent & 31;
-      }
-    } else {
-#pragma unroll
-      for (uint32_t i = 0; i < NS; ++i) {
+      } else {
+        ent[i] = 0xFFFFFFFFu;
         if (i < nvalid) {
-          const uint32_t l = e[i] < A ? cl[e[i]] : 0u;
+          const uint32_t l = sv < a.A ? a.cl[sv] : 0u;
           bad |= l == 0;
+          if (l) ent[i] = sv;
           L += l;
         }
       }
     }
-    if (bad) raise_status(status, HF_ERR_SYMBOL);
+    if (bad) raise_status(a.status, HF_ERR_SYMBOL);
 
-    // ---- shuffle-merge offsets: workgroup scan --------------------------------
+    // ---- shuffle-merge offsets: workgroup scan ---------------------------------
     uint32_t B;
     const uint32_t P = block_exclusive_scan<kEncWaves>(L, sh.wtot, &B);
-    if (tid == 0) store_agent(&lookback[tile], (tile == 0 ? kFlagIncl : kFlagAgg) | (uint64_t)B);
+    if (!last_tile) raw.load(a.sym, s0 + T, s_hi, a.vec_ok != 0);  // next tile, in flight meanwhile
 
-    // ---- reduce-merge into the tile buffer ------------------------------------
-    {
+    // ---- reduce-merge ---------------------------------------------------------
+    if (MODE != kModeWide) {
       uint64_t acc = 0;
       uint32_t nb = P & 31;
-      uint32_t wi = P >> 5;
-      if (packed) {
+      uint64_t wi = P >> 5;
 #pragma unroll
-        for (uint32_t i = 0; i < NS; ++i) push_bits(acc, nb, wi, buf, e[i] >> 5, e[i] & 31);
-      } else {
-#pragma unroll
-        for (uint32_t i = 0; i < NS; ++i) {
-          const uint32_t s = e[i];
-          if (i >= nvalid || s >= A) continue;
-          const uint32_t l = cl[s];
-          const uint64_t c = cw[s];
-          if (l > 32) {
-            push_bits(acc, nb, wi, buf, (uint32_t)(c >> 32), l - 32);
-            push_bits(acc, nb, wi, buf, (uint32_t)c, 32);
-          } else if (l > 0) {
-            push_bits(acc, nb, wi, buf, (uint32_t)c, l);
-          }
+      for (uint32_t i = 0; i < NS; ++i) {
+        if (MODE == kModeTable) {
+          push_bits(acc, nb, wi, buf, ~0ull, ent[i] >> 5, ent[i] & 31);
+        } else if (ent[i] != 0xFFFFFFFFu) {
+          push_bits(acc, nb, wi, buf, ~0ull, (uint32_t)a.cw[ent[i]], a.cl[ent[i]]);
         }
       }
       if (nb) atomicOr(&buf[wi], (uint32_t)(acc << (32 - nb)));
-    }
-    __syncthreads();
-
-    // ---- tail record + decoupled look-back (wave 0) ----------------------------
-    if (wave == 0) {
-      if (lane == 0 && !last) {
-        uint32_t tail;
-        if (B >= 32) {
-          const uint32_t o = B & 31, w = (B >> 5) - 1;
-          tail = o ? ((buf[w] << o) | (buf[w + 1] >> (32 - o))) : buf[w];
-        } else {
-          tail = B ? (buf[0] >> (32 - B)) : 0u;
-        }
-        store_agent(&tails[tile], kTailValid | tail);
-      }
-      uint64_t G = 0;
-      uint32_t spins = 0;
-      if (tile > 0) {
-        int64_t top = (int64_t)tile - 1;
-        for (;;) {
-          const int64_t idx = top - (int64_t)lane;
-          const uint64_t v = idx >= 0 ? load_agent(&lookback[idx]) : kFlagIncl;
-          const uint64_t flag = v >> 62;
-          const uint64_t incl = __ballot(flag == 2);
-          const uint64_t empty = __ballot(flag == 0);
-          const int fi = incl ? __ffsll((unsigned long long)incl) - 1 : 64;
-          const uint64_t need = fi >= 63 ? ~0ull : ((2ull << fi) - 1);
-          if ((empty & need) && ++spins < kSpinLimit) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          if (spins >= kSpinLimit) {
-            if (lane == 0) raise_status(status, HF_ERR_INTERNAL);
-            break;
-          }
-          G += wave_sum_u64((int)lane <= fi ? (v & kValueMask) : 0ull);
-          if (fi < 64) break;
-          top -= kWave;
-        }
-      }
-      if (lane == 0) {
-        if (tile > 0) store_agent(&lookback[tile], kFlagIncl | (G + B));
-        sh.G = G;
-        uint32_t pred = 0;
-        if (tile > 0 && (G & 31)) {
-          uint64_t tv;
-          for (uint32_t k = 0;; ++k) {
-            tv = load_agent(&tails[tile - 1]);
-            if (tv & kTailValid) break;
-            if (k >= kSpinLimit) {
-              raise_status(status, HF_ERR_INTERNAL);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-          pred = (uint32_t)tv;
-        }
-        sh.pred_tail = pred;
+    } else if (P + L > (B > 32 ? B - 32 : 0u)) {
+      // lanes holding the tile's last 32 bits build its tail record
+      uint32_t p = P;
+#pragma unroll
+      for (uint32_t i = 0; i < NS; ++i) {
+        if (ent[i] == 0xFFFFFFFFu) continue;
+        const uint32_t l = a.cl[ent[i]];
+        const uint32_t part = tail_part(a.cw[ent[i]], l, p, B);
+        if (part) atomicOr(&sh.tailw, part);
+        p += l;
       }
     }
     __syncthreads();
 
-    // ---- gathering: funnel-shifted coalesced stores ------------------------------
-    const uint64_t G = sh.G;
-    const uint32_t q = (uint32_t)(G & 31);
-    const uint64_t w0 = G >> 5;
-    const uint64_t end_bit = G + B;
-    uint64_t wend = (end_bit + 31) >> 5;
-    if (!last && (end_bit & 31)) wend -= 1;  // the next tile owns the shared word
-    const uint32_t nw = (uint32_t)(wend - w0);
-    const uint32_t pred = sh.pred_tail;
-    for (uint32_t i = tid; i < nw; i += kEncThreads) {
-      uint32_t v;
-      if (q == 0) {
-        v = buf[i];
+    // ---- this tile's last 32 bits, for the next tile of the slab -------------------
+    if (tid == 0) {
+      uint32_t tail;
+      if (MODE == kModeWide) {
+        tail = sh.tailw;
+      } else if (B >= 32) {
+        const uint32_t o = B & 31, w = (B >> 5) - 1;
+        tail = o ? ((buf[w] << o) | (buf[w + 1] >> (32 - o))) : buf[w];
       } else {
-        const uint32_t hi = i == 0 ? pred : buf[i - 1];
-        v = (hi << (32 - q)) | (buf[i] >> q);
+        tail = B ? (buf[0] >> (32 - B)) : 0u;
       }
-      const uint64_t wi = w0 + i;
-      if (wi < cap_words) out[wi] = v;
+      sh.tail[(t + 1) & 1] = tail;
     }
-    if (s0 < n && (s0 & ((1ull << chunk_log2) - 1)) == 0) offsets[s0 >> chunk_log2] = G + P;
-    if (last && tid == 0) {
-      offsets[nchunks] = end_bit;
-      if (end_bit > 32ull * cap_words) raise_status(status, HF_ERR_CAPACITY);
+
+    // ---- gathering ----------------------------------------------------------------
+    const uint64_t Gt = G + run;
+    const uint32_t q = (uint32_t)(Gt & 31);
+    const uint64_t w0 = Gt >> 5;
+    const uint64_t end_bit = Gt + B;
+    const bool stream_end = last_slab && last_tile;
+    uint64_t wend = (end_bit + 31) >> 5;
+    if (!stream_end && (end_bit & 31)) wend -= 1;  // the next tile owns the shared word
+    const uint32_t nw = (uint32_t)(wend - w0);
+    const uint32_t pred = sh.tail[t & 1];
+    if (MODE != kModeWide) {
+      for (uint32_t i = tid; i < nw; i += kEncThreads) {
+        uint32_t v;
+        if (q == 0) {
+          v = buf[i];
+        } else {
+          const uint32_t hi = i == 0 ? pred : buf[i - 1];
+          v = (hi << (32 - q)) | (buf[i] >> q);
+        }
+        const uint64_t wi = w0 + i;
+        if (wi < a.cap_words) a.out[wi] = v;
+      }
+    } else {
+      for (uint32_t i = tid; i < nw; i += kEncThreads) {
+        const uint64_t wi = w0 + i;
+        if (wi < a.cap_words) a.out[wi] = (i == 0 && q) ? (pred << (32 - q)) : 0u;
+      }
+      __syncthreads();
+      const uint64_t limit = wend < a.cap_words ? wend : a.cap_words;
+      const uint64_t pos = Gt + P;
+      uint64_t acc = 0;
+      uint32_t nb = (uint32_t)(pos & 31);
+      uint64_t wi = pos >> 5;
+#pragma unroll
+      for (uint32_t i = 0; i < NS; ++i) {
+        if (ent[i] == 0xFFFFFFFFu) continue;
+        const uint32_t l = a.cl[ent[i]];
+        const uint64_t c = a.cw[ent[i]];
+        if (l > 32) {
+          push_bits(acc, nb, wi, a.out, limit, (uint32_t)(c >> 32), l - 32);
+          push_bits(acc, nb, wi, a.out, limit, (uint32_t)c, 32);
+        } else {
+          push_bits(acc, nb, wi, a.out, limit, (uint32_t)c, l);
+        }
+      }
+      if (nb && wi < limit) atomicOr(&a.out[wi], (uint32_t)(acc << (32 - nb)));
     }
+    if (s0 < s_hi && (s0 & ((1ull << a.chunk_log2) - 1)) == 0) a.offsets[s0 >> a.chunk_log2] = Gt + P;
+    if (stream_end && tid == 0) {
+      a.offsets[a.nchunks] = end_bit;
+      if (end_bit > 32ull * a.cap_words) raise_status(a.status, HF_ERR_CAPACITY);
+    }
+    run += B;
     __syncthreads();
-    // clear what this tile used (one word past the content is read above)
-    const uint32_t used = (B + 31) / 32 + 1;
-    for (uint32_t i = tid; i < used; i += kEncThreads) buf[i] = 0;
+    if (MODE != kModeWide) {
+      // clear what this tile used (one word past the content is read above)
+      const uint32_t used = (B + 31) / 32 + 1;
+      for (uint32_t i = tid; i < used; i += kEncThreads) buf[i] = 0;
+    } else if (tid == 0) {
+      sh.tailw = 0;
+    }
   }
+}
+
+template <int R, int SB>
+__global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
+  constexpr uint32_t T = kEncThreads << R;
+  extern __shared__ uint32_t lds[];
+  __shared__ EncShared sh;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+  const uint32_t lmax = (uint32_t)a.info[1];
+  const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
+  const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
+  uint32_t* tab = lds;
+  uint32_t* buf = lds + (a.A <= kTableMaxAlphabet ? a.A : 0u);
+  if (mode == kModeTable)
+    for (uint32_t s = tid; s < a.A; s += kEncThreads) {
+      const uint32_t l = a.cl[s];
+      tab[s] = l ? (((uint32_t)a.cw[s]) << 5) | l : 0u;
+    }
+  if (mode != kModeWide)
+    for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
+  // this slab's first bit: the bit totals of all earlier slabs
+  uint64_t G = 0;
+  for (uint32_t k = tid; k < g; k += kEncThreads) G += a.bits[k];
+  G = wave_sum_u64(G);
+  if (lane_id() == 0) sh.red[tid / kWave] = G;
+  if (tid == 0) {
+    sh.tail[0] = g > 0 ? a.tails[g - 1] : 0u;
+    sh.tailw = 0;
+  }
+  __syncthreads();
+  G = 0;
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
+  if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, sh, g, G);
+  else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, sh, g, G);
+  else encode_slab<R, SB, kModeWide>(a, tab, buf, sh, g, G);
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-inline uint64_t tiles_for(uint64_t n, uint32_t r) {
-  const uint64_t T = (uint64_t)kEncThreads << r;
-  return (n + T - 1) / T;
-}
-
-using EncodeFn = void (*)(const void*, uint64_t, uint32_t, const uint8_t*, const uint64_t*,
-                          const uint64_t*, uint32_t*, uint64_t, uint64_t*, uint32_t, uint64_t,
-                          uint32_t*, uint64_t*, uint64_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+using EncodeFn = void (*)(EncArgs);
 
 template <int R>
 EncodeFn pick_sb(uint32_t sb) {
@@ -332,7 +447,12 @@ EncodeFn pick(uint32_t r, uint32_t sb) {
   }
 }
 
-// Occupancy-sized persistent grid, cached per kernel and LDS size.
+size_t encode_lds_bytes(uint32_t A, uint32_t r) {
+  const size_t T = (size_t)kEncThreads << r;
+  return 4 * ((A <= kTableMaxAlphabet ? (size_t)A : 0) + T + 2);
+}
+
+// Resident workgroups per CU, cached per kernel and LDS size.
 struct OccEntry {
   const void* fn;
   size_t lds;
@@ -340,8 +460,10 @@ struct OccEntry {
 };
 OccEntry g_occ[64];
 int g_nocc = 0;
+std::mutex g_occ_mu;
 
 int blocks_per_cu(EncodeFn fn, size_t lds) {
+  std::lock_guard<std::mutex> lock(g_occ_mu);
   for (int i = 0; i < g_nocc; ++i)
     if (g_occ[i].fn == (const void*)fn && g_occ[i].lds == lds) return g_occ[i].blocks;
   if (lds > (64u << 10))
@@ -355,25 +477,19 @@ int blocks_per_cu(EncodeFn fn, size_t lds) {
 
 }  // namespace
 
-size_t encode_workspace_bytes(uint64_t n, uint32_t r) {
-  const uint64_t nt = tiles_for(n, r);
-  return 256 + 2 * align256(nt * 8);
+int encode_blocks_per_cu(uint32_t alphabet, uint32_t sym_bytes) {
+  const uint32_t r = kEncDefaultR;
+  return blocks_per_cu(pick(r, sym_bytes), encode_lds_bytes(alphabet, r));
 }
 
-EncodeWorkspace encode_workspace_layout(void* ws, uint64_t n, uint32_t r) {
-  const uint64_t nt = tiles_for(n, r);
-  char* p = (char*)ws;
-  EncodeWorkspace w;
-  w.ticket = (uint32_t*)p;
-  w.lookback = (uint64_t*)(p + 256);
-  w.tails = (uint64_t*)(p + 256 + align256(nt * 8));
-  return w;
+size_t encode_workspace_bytes(uint32_t nslabs) {
+  return align256((size_t)nslabs * 8) + align256((size_t)nslabs * 4);
 }
 
 hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
-                         uint32_t chunk_log2, uint32_t r, uint32_t* out, uint64_t cap_words,
-                         uint64_t* offsets, void* ws, uint32_t* status, int num_cus,
-                         hipStream_t stream, const KernelTimer& timer) {
+                         uint32_t chunk_log2, uint32_t r, uint32_t nslabs, const uint32_t* slab_hist,
+                         uint32_t* out, uint64_t cap_words, uint64_t* offsets, void* ws,
+                         uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
   const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
   if (n == 0) {
     hipError_t e = launch_fill_u64(offsets, 1, 0, stream);
@@ -381,27 +497,51 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
     timer.after(stream);
     return e;
   }
-  const uint64_t ntiles = tiles_for(n, r);
-  const EncodeWorkspace w = encode_workspace_layout(ws, n, r);
-  // one fill clears the ticket and every look-back and tail record
-  const uint64_t clear_words = (256 + 2 * align256(ntiles * 8)) / 8;
-  hipError_t e = launch_fill_u64((uint64_t*)ws, clear_words, 0, stream);
+  const uint64_t nblocks = (n + kSlabBlock - 1) / kSlabBlock;
+  uint64_t* bits = (uint64_t*)ws;
+  uint32_t* tails = (uint32_t*)((char*)ws + align256((size_t)nslabs * 8));
+  const uint32_t A = book.alphabet;
+
+  SlabArgs s;
+  s.sym = sym;
+  s.n = n;
+  s.nblocks = nblocks;
+  s.nslabs = nslabs;
+  s.A = A;
+  s.cl = book.cl;
+  s.cw = book.cw;
+  s.slab_hist = slab_hist;
+  s.bits = bits;
+  s.tails = tails;
+  s.status = status;
+  if (sym_bytes == 1) slab_bits_kernel<1><<<nslabs, kPreThreads, 0, stream>>>(s);
+  else slab_bits_kernel<2><<<nslabs, kPreThreads, 0, stream>>>(s);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  const uint32_t T = (uint32_t)kEncThreads << r;
-  const uint32_t A = book.alphabet;
-  const uint32_t table_ok = A <= kPackedMaxAlphabet ? 1u : 0u;
-  const size_t packed_words = table_ok ? (size_t)A + (T * kPackedMaxLen + 31) / 32 + 2 : 0;
-  const size_t wide_words = 2 * (size_t)T + 2;
-  const size_t lds = 4 * (packed_words > wide_words ? packed_words : wide_words);
-  const uint32_t vec_ok = ((uintptr_t)sym % 16) == 0 ? 1u : 0u;
+  EncArgs a;
+  a.sym = sym;
+  a.n = n;
+  a.nblocks = nblocks;
+  a.nslabs = nslabs;
+  a.A = A;
+  a.cl = book.cl;
+  a.cw = book.cw;
+  a.info = book.info;
+  a.bits = bits;
+  a.tails = tails;
+  a.out = out;
+  a.cap_words = cap_words;
+  a.offsets = offsets;
+  a.chunk_log2 = chunk_log2;
+  a.nchunks = nchunks;
+  a.status = status;
+  a.vec_ok = ((uintptr_t)sym % 16) == 0 ? 1u : 0u;
   EncodeFn fn = pick(r, sym_bytes);
-  const int nb = blocks_per_cu(fn, lds);
-  const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)num_cus * nb);
+  const size_t lds = encode_lds_bytes(A, r);
+  (void)blocks_per_cu(fn, lds);  // sets the LDS attribute when above 64 KiB
   timer.before(stream);
-  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kEncThreads), lds, stream, sym, n, A, book.cl,
-                     book.cw, book.info, out, cap_words, offsets, chunk_log2, nchunks, w.ticket,
-                     w.lookback, w.tails, (uint32_t)ntiles, status, table_ok, vec_ok);
+  hipLaunchKernelGGL(fn, dim3(nslabs), dim3(kEncThreads), lds, stream, a);
   e = hipGetLastError();
   timer.after(stream);
   return e;

@@ -60,42 +60,74 @@ __device__ __forceinline__ void hist_count_vec(uint32_t* sub, uint4 v, uint32_t 
   }
 }
 
-// One launch counts bins [lo, lo + W) of a slab-partitioned input.  The
-// first `head` symbols (up to the first 16-byte boundary) and the tail after
-// the last whole vector are counted by workgroup 0 with scalar loads.
+// Counts symbols [s_lo, s_hi) into the LDS window: scalar head up to the
+// first 16-byte boundary, 16-byte vectors (four in flight per lane), scalar
+// tail.
 template <int SB>
-__global__ __launch_bounds__(kHistThreads) void histogram_kernel(
-    const void* __restrict__ sym, uint64_t n, uint64_t head, uint32_t A, uint32_t lo, uint32_t W,
-    uint32_t R, uint32_t* __restrict__ hist, uint32_t* __restrict__ status) {
-  extern __shared__ uint32_t sub[];
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < W * R; i += blockDim.x) sub[i] = 0;
-  __syncthreads();
-
+__device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict__ sym, uint64_t s_lo,
+                                           uint64_t s_hi, uint32_t lo, uint32_t W, uint32_t A, uint32_t R,
+                                           uint32_t rep, bool& bad) {
   constexpr uint32_t kPerVec = 16 / SB;
-  const uint32_t rep = tid & (R - 1);
-  bool bad = false;
-  const uint64_t nbody = (n - head) / kPerVec;
-  const uint4* body = (const uint4*)((const char*)sym + head * SB);
-  const uint64_t per = (nbody + gridDim.x - 1) / gridDim.x;
-  const uint64_t beg = (uint64_t)blockIdx.x * per;
-  const uint64_t end = min(nbody, beg + per);
-
-  uint64_t v = beg + tid;
+  const uint32_t tid = threadIdx.x;
+  const uintptr_t addr = (uintptr_t)sym + s_lo * SB;
+  uint64_t head = ((16 - (addr & 15)) & 15) / SB;
+  if (head > s_hi - s_lo) head = s_hi - s_lo;
+  const uint64_t nvec = (s_hi - s_lo - head) / kPerVec;
+  const uint4* body = (const uint4*)((const char*)sym + (s_lo + head) * SB);
+  uint64_t v = tid;
   constexpr int kUnroll = 4;
-  for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < end; v += kUnroll * (uint64_t)blockDim.x) {
+  for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < nvec; v += kUnroll * (uint64_t)blockDim.x) {
     uint4 q[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) hist_count_vec<SB>(sub, q[u], lo, W, A, R, rep, bad);
   }
-  for (; v < end; v += blockDim.x) hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
+  for (; v < nvec; v += blockDim.x) hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
+  for (uint64_t i = tid; i < head; i += blockDim.x) hist_count(sub, sym_load<SB>(sym, s_lo + i), lo, W, A, R, rep, bad);
+  for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x)
+    hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+}
 
-  if (blockIdx.x == 0) {
-    for (uint64_t i = tid; i < head; i += blockDim.x) hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
-    for (uint64_t i = head + nbody * kPerVec + tid; i < n; i += blockDim.x)
-      hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+// One launch counts bins [lo, lo + W).  Workgroup w takes the contiguous
+// slabs [w*S/G, (w+1)*S/G); with slab_hist it stores each slab's counts
+// (differences of the running LDS totals, so the LDS is never cleared in
+// between) and, at the end, adds its totals to the global histogram.
+template <int SB>
+__global__ __launch_bounds__(kHistThreads) void histogram_kernel(
+    const void* __restrict__ sym, uint64_t n, uint32_t A, uint32_t lo, uint32_t W, uint32_t R,
+    uint32_t nslabs, uint64_t nblocks, uint32_t* __restrict__ hist, uint32_t* __restrict__ slab_hist,
+    uint32_t* __restrict__ status) {
+  extern __shared__ uint32_t sub[];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < W * R; i += blockDim.x) sub[i] = 0;
+  __syncthreads();
+
+  const uint32_t rep = tid & (R - 1);
+  bool bad = false;
+  const uint64_t g0 = (uint64_t)blockIdx.x * nslabs / gridDim.x;
+  const uint64_t g1 = (uint64_t)(blockIdx.x + 1) * nslabs / gridDim.x;
+  uint32_t prev[kSlabHistMaxAlphabet / kHistThreads];
+#pragma unroll
+  for (int k = 0; k < (int)(kSlabHistMaxAlphabet / kHistThreads); ++k) prev[k] = 0;
+  for (uint64_t g = g0; g < g1; ++g) {
+    const uint64_t s_lo = slab_begin(g, nblocks, nslabs, n);
+    const uint64_t s_hi = slab_begin(g + 1, nblocks, nslabs, n);
+    hist_range<SB>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
+    if (slab_hist) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < (int)(kSlabHistMaxAlphabet / kHistThreads); ++k) {
+        const uint32_t b = tid + k * kHistThreads;
+        if (b < W) {
+          uint32_t c = 0;
+          for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+          slab_hist[g * A + lo + b] = c - prev[k];
+          prev[k] = c;
+        }
+      }
+      __syncthreads();
+    }
   }
   __syncthreads();
 
@@ -138,29 +170,38 @@ static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
 }
 
 hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t A,
-                            uint32_t* hist, uint32_t* status, int num_cus, hipStream_t stream,
-                            const KernelTimer& timer) {
+                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* status,
+                            int num_cus, hipStream_t stream, const KernelTimer& timer) {
   hipError_t e = launch_fill_u32(hist, A, 0u, stream);
   if (e != hipSuccess) return e;
   uint32_t W, R;
   hist_plan(A, &W, &R);
   const size_t lds = (size_t)W * R * sizeof(uint32_t);
-  const uint64_t per_vec = 16 / sym_bytes;
-  const uintptr_t addr = (uintptr_t)sym;
-  uint64_t head = ((16 - (addr & 15)) & 15) / sym_bytes;
-  if (head > n) head = n;
-  const uint64_t nbody = (n - head) / per_vec;
-  // enough vectors per workgroup to amortize the LDS clear and flush
-  const uint64_t want = (nbody + 4ull * kHistThreads * 8 - 1) / (4ull * kHistThreads * 8);
+  const uint64_t nblocks = (n + kSlabBlock - 1) / kSlabBlock;
   const uint32_t wgs_per_cu = (lds <= (64u << 10)) ? 2u : 1u;
-  uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)num_cus * wgs_per_cu, want > 0 ? want : 1);
+  uint64_t grid = (uint64_t)num_cus * wgs_per_cu;
+  if (slab_hist) {
+    if (grid > nslabs) grid = nslabs;
+  } else {
+    // no per-slab output: one slab of at least 4 blocks per workgroup
+    const uint64_t want = (nblocks + 3) / 4;
+    if (grid > want) grid = want;
+    if (grid < 1) grid = 1;
+    nslabs = (uint32_t)grid;
+  }
+  if (lds > (64u << 10)) {
+    (void)hipFuncSetAttribute((const void*)histogram_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)histogram_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
   timer.before(stream);
   for (uint32_t lo = 0; lo < A; lo += W) {
     const uint32_t w = std::min(W, A - lo);
     if (sym_bytes == 1)
-      histogram_kernel<1><<<grid, kHistThreads, lds, stream>>>(sym, n, head, A, lo, w, R, hist, status);
+      histogram_kernel<1><<<(uint32_t)grid, kHistThreads, lds, stream>>>(sym, n, A, lo, w, R, nslabs, nblocks, hist,
+                                                                         slab_hist, status);
     else
-      histogram_kernel<2><<<grid, kHistThreads, lds, stream>>>(sym, n, head, A, lo, w, R, hist, status);
+      histogram_kernel<2><<<(uint32_t)grid, kHistThreads, lds, stream>>>(sym, n, A, lo, w, R, nslabs, nblocks, hist,
+                                                                         slab_hist, status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -18,7 +18,17 @@ constexpr int kEncMinR = 1;
 constexpr int kEncMaxR = 6;
 constexpr int kEncDefaultR = 4;
 constexpr uint32_t kPackedMaxLen = 27;        // cw << 5 | cl fits 32 bits
-constexpr uint32_t kPackedMaxAlphabet = 16384;  // packed table kept in LDS up to this alphabet
+
+// Slab partition shared by the histogram and the encoder: slab g of S
+// covers blocks [g*nb/S, (g+1)*nb/S) of kSlabBlock symbols, nb = ceil(n / kSlabBlock).
+constexpr uint64_t kSlabBlock = 4096;
+constexpr uint32_t kSlabHistMaxAlphabet = 4096;  // per-slab counts kept up to this alphabet
+constexpr uint32_t kMaxSlabs = 16384;  // each encoder workgroup sums all earlier slab totals
+
+__host__ __device__ inline uint64_t slab_begin(uint64_t g, uint64_t nblocks, uint64_t nslabs, uint64_t n) {
+  const uint64_t s = (g * nblocks / nslabs) * kSlabBlock;
+  return s < n ? s : n;
+}
 
 // Records a pair of events around one kernel launch when armed.
 struct KernelTimer {
@@ -36,8 +46,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t stream);
 
 hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
-                            uint32_t* hist, uint32_t* status, int num_cus, hipStream_t stream,
-                            const KernelTimer& timer);
+                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* status,
+                            int num_cus, hipStream_t stream, const KernelTimer& timer);
 
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.
@@ -46,18 +56,16 @@ size_t codebook_workspace_bytes(uint32_t alphabet);
 hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer);
 
-struct EncodeWorkspace {
-  uint32_t* ticket;    // 1 word
-  uint64_t* lookback;  // [ntiles] {flag:2 | value:62}
-  uint64_t* tails;     // [ntiles] {valid:32 | last 32 content bits}
-};
-size_t encode_workspace_bytes(uint64_t n, uint32_t r);
-EncodeWorkspace encode_workspace_layout(void* ws, uint64_t n, uint32_t r);
+// Encoder workspace: per-slab bit totals and last-32-bit records.
+size_t encode_workspace_bytes(uint32_t nslabs);
+
+// Resident workgroups per CU of the default encoder for this alphabet.
+int encode_blocks_per_cu(uint32_t alphabet, uint32_t sym_bytes);
 
 hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
-                         uint32_t chunk_log2, uint32_t r, uint32_t* out, uint64_t cap_words,
-                         uint64_t* offsets, void* ws, uint32_t* status, int num_cus,
-                         hipStream_t stream, const KernelTimer& timer);
+                         uint32_t chunk_log2, uint32_t r, uint32_t nslabs, const uint32_t* slab_hist,
+                         uint32_t* out, uint64_t cap_words, uint64_t* offsets, void* ws,
+                         uint32_t* status, hipStream_t stream, const KernelTimer& timer);
 
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
                                uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,

@@ -62,12 +62,14 @@ _lib.hf_status_string.argtypes = [_U32]
 _lib.hf_status_string.restype = ctypes.c_char_p
 _lib.hf_time_next_main_kernel.argtypes = [_P, _P]
 _lib.hf_time_next_main_kernel.restype = ctypes.c_int
-_lib.hf_histogram.argtypes = [_P, _U64, _U32, _U32, _P, _P, _SZ, _P, _P]
+_lib.hf_slab_count.argtypes = [_U64, _U32]
+_lib.hf_slab_count.restype = _U32
+_lib.hf_histogram.argtypes = [_P, _U64, _U32, _U32, _P, _U32, _P, _P, _SZ, _P, _P]
 _lib.hf_histogram.restype = ctypes.c_int
 _lib.hf_build_codebook.argtypes = [_P, ctypes.POINTER(hf_codebook), _P, _SZ, _P, _P]
 _lib.hf_build_codebook.restype = ctypes.c_int
-_lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _P, _U64, _P, _P,
-                           _SZ, _P, _P]
+_lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _U32, _P, _P, _U64,
+                           _P, _P, _SZ, _P, _P]
 _lib.hf_encode.restype = ctypes.c_int
 _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
                                  _SZ, _P, _P]
@@ -115,6 +117,10 @@ def hf_workspace_bytes(n: int, alphabet: int, chunk_symbols: int = 4096) -> int:
 
 def hf_bound_words(n: int, alphabet: int) -> int:
     return int(_lib.hf_bound_words(n, alphabet))
+
+
+def hf_slab_count(n: int, alphabet: int) -> int:
+    return int(_lib.hf_slab_count(n, alphabet))
 
 
 def hf_reduction_factor(beta: float) -> int:
@@ -179,14 +185,18 @@ class Codebook:
 
 
 def hf_histogram(sym: torch.Tensor, alphabet: int, hist: torch.Tensor | None = None,
+                 nslabs: int = 0, slab_hist: torch.Tensor | None = None,
                  ws: torch.Tensor | None = None, status: torch.Tensor | None = None) -> torch.Tensor:
+    """Histogram of `sym`; with `slab_hist` (int32[nslabs * alphabet]) also
+    the per-slab counts for hf_encode."""
     sb = _sym_bytes(sym)
     if hist is None:
         hist = torch.empty(alphabet, dtype=torch.int32, device=sym.device)
     if status is None:
         status = new_status(sym.device)
-    _check(_lib.hf_histogram(_ptr(sym), sym.numel(), sb, alphabet, _ptr(hist), _ptr(ws),
-                             0 if ws is None else ws.numel(), _ptr(status), _stream()), "hf_histogram")
+    _check(_lib.hf_histogram(_ptr(sym), sym.numel(), sb, alphabet, _ptr(hist), nslabs, _ptr(slab_hist),
+                             _ptr(ws), 0 if ws is None else ws.numel(), _ptr(status), _stream()),
+           "hf_histogram")
     return hist
 
 
@@ -204,7 +214,8 @@ def hf_build_codebook(hist: torch.Tensor, book: Codebook | None = None, ws: torc
 
 def hf_encode(sym: torch.Tensor, book: Codebook, chunk_symbols: int = 4096, reduce_log2: int = 0,
               out: torch.Tensor | None = None, offsets: torch.Tensor | None = None,
-              ws: torch.Tensor | None = None, status: torch.Tensor | None = None):
+              ws: torch.Tensor | None = None, status: torch.Tensor | None = None,
+              nslabs: int = 0, slab_hist: torch.Tensor | None = None):
     """Returns (out words as int32 tensor, chunk bit offsets as int64 tensor)."""
     sb = _sym_bytes(sym)
     n = sym.numel()
@@ -218,8 +229,9 @@ def hf_encode(sym: torch.Tensor, book: Codebook, chunk_symbols: int = 4096, redu
     if status is None:
         status = new_status(sym.device)
     s = book.struct()
-    _check(_lib.hf_encode(_ptr(sym), n, sb, ctypes.byref(s), chunk_symbols, reduce_log2, _ptr(out),
-                          out.numel(), _ptr(offsets), _ptr(ws), ws.numel(), _ptr(status), _stream()),
+    _check(_lib.hf_encode(_ptr(sym), n, sb, ctypes.byref(s), chunk_symbols, reduce_log2, nslabs,
+                          _ptr(slab_hist), _ptr(out), out.numel(), _ptr(offsets), _ptr(ws), ws.numel(),
+                          _ptr(status), _stream()),
            "hf_encode")
     return out, offsets
 
@@ -242,36 +254,41 @@ def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor,
 
 class Encoder:
     """Pre-allocated buffers for repeated hist -> codebook -> encode passes
-    over streams of at most `max_n` symbols (nothing is allocated per call)."""
+    over streams of exactly `n` symbols (nothing is allocated per call).
+    When the alphabet allows it, the histogram pass also records per-slab
+    counts that let the encoder place every slab without re-reading the
+    input."""
 
-    def __init__(self, max_n: int, alphabet: int, chunk_symbols: int = 4096, reduce_log2: int = 0,
-                 device="cuda"):
-        self.max_n = max_n
+    def __init__(self, n: int, alphabet: int, chunk_symbols: int = 4096, reduce_log2: int = 0,
+                 device="cuda", use_slab_hist: bool = True):
+        self.n = n
         self.alphabet = alphabet
         self.chunk = chunk_symbols
         self.r = reduce_log2
         self.hist = torch.empty(alphabet, dtype=torch.int32, device=device)
         self.book = Codebook.empty(alphabet, device)
-        self.ws = new_workspace(max_n, alphabet, chunk_symbols, device)
+        self.ws = new_workspace(n, alphabet, chunk_symbols, device)
         self.status = new_status(device)
-        self.out = torch.empty(max(1, hf_bound_words(max_n, alphabet)), dtype=torch.int32, device=device)
-        self.offsets = torch.empty((max_n + chunk_symbols - 1) // chunk_symbols + 1, dtype=torch.int64,
+        self.out = torch.empty(max(1, hf_bound_words(n, alphabet)), dtype=torch.int32, device=device)
+        self.offsets = torch.empty((n + chunk_symbols - 1) // chunk_symbols + 1, dtype=torch.int64,
                                    device=device)
+        self.nslabs = hf_slab_count(n, alphabet) if use_slab_hist else 0
+        self.slab_hist = (torch.empty(self.nslabs * alphabet, dtype=torch.int32, device=device)
+                          if self.nslabs else None)
 
     def run(self, sym: torch.Tensor, timers=None):
         """One pass of the whole path.  `timers` (optional) maps 'hist',
         'codebook', 'encode' to (before, after) torch.cuda.Event pairs
         recorded around each stage's main kernel."""
-        n = sym.numel()
-        assert n <= self.max_n
-        nch = (n + self.chunk - 1) // self.chunk
+        assert sym.numel() == self.n
         if timers and "hist" in timers:
             hf_time_next_main_kernel(*timers["hist"])
-        hf_histogram(sym, self.alphabet, self.hist, self.ws, self.status)
+        hf_histogram(sym, self.alphabet, self.hist, self.nslabs, self.slab_hist, self.ws, self.status)
         if timers and "codebook" in timers:
             hf_time_next_main_kernel(*timers["codebook"])
         hf_build_codebook(self.hist, self.book, self.ws, self.status)
         if timers and "encode" in timers:
             hf_time_next_main_kernel(*timers["encode"])
-        hf_encode(sym, self.book, self.chunk, self.r, self.out, self.offsets[: nch + 1], self.ws, self.status)
-        return self.out, self.offsets[: nch + 1]
+        hf_encode(sym, self.book, self.chunk, self.r, self.out, self.offsets, self.ws, self.status,
+                  self.nslabs, self.slab_hist)
+        return self.out, self.offsets

@@ -71,15 +71,28 @@ def test_reduction_factor_rule_matches_table4(lib):
 
 def test_host_argument_checks_return_before_device_work(lib):
     P = ctypes.c_void_p
-    lib.hf_histogram.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P,
-                                 ctypes.c_size_t, P, P]
-    dummy = P(0x1000)
+    U32, U64, SZ = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    lib.hf_histogram.argtypes = [P, U64, U32, U32, P, U32, P, P, SZ, P, P]
+    d = P(0x1000)
     # sym_bytes 3, alphabet 0, uint8 with alphabet > 256, n >= 2^32
-    assert lib.hf_histogram(dummy, 10, 3, 16, dummy, None, 0, dummy, None) == 1
-    assert lib.hf_histogram(dummy, 10, 2, 0, dummy, None, 0, dummy, None) == 1
-    assert lib.hf_histogram(dummy, 10, 1, 300, dummy, None, 0, dummy, None) == 1
-    assert lib.hf_histogram(dummy, 1 << 32, 2, 16, dummy, None, 0, dummy, None) == 1
+    assert lib.hf_histogram(d, 10, 3, 16, d, 0, None, None, 0, d, None) == 1
+    assert lib.hf_histogram(d, 10, 2, 0, d, 0, None, None, 0, d, None) == 1
+    assert lib.hf_histogram(d, 10, 1, 300, d, 0, None, None, 0, d, None) == 1
+    assert lib.hf_histogram(d, 1 << 32, 2, 16, d, 0, None, None, 0, d, None) == 1
     # misaligned 16-bit symbols
-    assert lib.hf_histogram(P(0x1001), 10, 2, 16, dummy, None, 0, dummy, None) == 1
+    assert lib.hf_histogram(P(0x1001), 10, 2, 16, d, 0, None, None, 0, d, None) == 1
+    # per-slab counts: need 1 <= nslabs <= blocks and alphabet <= 4096
+    assert lib.hf_histogram(d, 10_000, 2, 16, d, 0, d, None, 0, d, None) == 1
+    assert lib.hf_histogram(d, 10_000, 2, 16, d, 4, d, None, 0, d, None) == 1
+    assert lib.hf_histogram(d, 10_000, 2, 8192, d, 2, d, None, 0, d, None) == 1
     lib.hf_status_string.restype = ctypes.c_char_p
     assert b"argument" in lib.hf_status_string(1)
+
+
+def test_slab_count_bounds(lib):
+    lib.hf_slab_count.restype = ctypes.c_uint32
+    lib.hf_slab_count.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    assert lib.hf_slab_count(0, 1024) == 0
+    assert lib.hf_slab_count(1 << 20, 65536) == 0  # no per-slab counts for large alphabets
+    assert 1 <= lib.hf_slab_count(5000, 1024) <= 2  # at most one slab per 4096-symbol block
+    assert 1 <= lib.hf_slab_count(1 << 27, 1024) <= (1 << 27) // 4096

@@ -36,16 +36,27 @@ def _u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-def gpu_hist(x: np.ndarray, A: int, offset: int = 0):
+def slab_ranges(n: int, nslabs: int):
+    """Slab g covers 4096-symbol blocks [g*nb/S, (g+1)*nb/S) (include/hf.h)."""
+    nb = (n + 4095) // 4096
+    cut = [min(n, (g * nb // nslabs) * 4096) for g in range(nslabs + 1)]
+    return list(zip(cut[:-1], cut[1:]))
+
+
+def gpu_hist(x: np.ndarray, A: int, offset: int = 0, nslabs: int = 0):
     """Histogram of x on the GPU; `offset` > 0 places x at a misaligned
-    address inside a larger buffer."""
+    address inside a larger buffer; nslabs > 0 also returns per-slab counts."""
     buf = np.zeros(x.size + offset, dtype=x.dtype)
     buf[offset:] = x
     d = _dev(buf)[offset:]
     status = hf.new_status()
-    h = hf.hf_histogram(d, A, status=status)
+    sh = torch.full((max(1, nslabs) * A,), -1, dtype=torch.int32, device="cuda") if nslabs else None
+    h = hf.hf_histogram(d, A, nslabs=nslabs, slab_hist=sh, status=status)
     assert hf.read_status(status) == 0
-    return h.cpu().numpy().view(np.uint32)
+    h = h.cpu().numpy().view(np.uint32)
+    if nslabs:
+        return h, sh.cpu().numpy().view(np.uint32).reshape(nslabs, A)
+    return h
 
 
 def gpu_book(h: np.ndarray):
@@ -68,7 +79,8 @@ def assert_book_equal(book, ref: oracle.Codebook):
     assert np.array_equal(_u32(book.rev)[:m], ref.rev[:m])
 
 
-def gpu_encode(x: np.ndarray, book, chunk: int, r: int = 0, cap_words: int | None = None):
+def gpu_encode(x: np.ndarray, book, chunk: int, r: int = 0, cap_words: int | None = None,
+               nslabs: int = 0, slab_hist: np.ndarray | None = None):
     d = _dev(x)
     n = x.size
     cap = cap_words if cap_words is not None else hf.hf_bound_words(n, book.alphabet)
@@ -77,26 +89,41 @@ def gpu_encode(x: np.ndarray, book, chunk: int, r: int = 0, cap_words: int | Non
     offsets = torch.full((nch + 1,), -1, dtype=torch.int64, device="cuda")
     ws = hf.new_workspace(n, book.alphabet, chunk)
     status = hf.new_status()
-    hf.hf_encode(d, book, chunk, r, out[:cap], offsets, ws, status)
+    sh = None if slab_hist is None else torch.from_numpy(slab_hist.reshape(-1).view(np.int32)).cuda()
+    hf.hf_encode(d, book, chunk, r, out[:cap], offsets, ws, status, nslabs=nslabs, slab_hist=sh)
     code = hf.read_status(status)
     return _u32(out), _u64(offsets), code
 
 
-def check_pipeline(x: np.ndarray, A: int, chunk: int, r: int = 0):
+def check_pipeline(x: np.ndarray, A: int, chunk: int, r: int = 0, slab_counts=None):
+    """GPU histogram (with per-slab counts when the alphabet allows),
+    codebook, and encoding both from those counts and without them, each
+    compared with the oracle."""
     ref_h = oracle.histogram(x, A)
-    h = gpu_hist(x, A)
+    nslabs = hf.hf_slab_count(x.size, A)
+    if nslabs:
+        h, sh = gpu_hist(x, A, nslabs=nslabs)
+        for g, (lo, hi) in enumerate(slab_ranges(x.size, nslabs)):
+            assert np.array_equal(sh[g], oracle.histogram(x[lo:hi], A)), g
+    else:
+        h, sh = gpu_hist(x, A), None
     assert np.array_equal(h, ref_h)
     ref = oracle.codebook(ref_h)
     book, code = gpu_book(h)
     assert code == 0
     assert_book_equal(book, ref)
-    words, offs, code = gpu_encode(x, book, chunk, r)
-    assert code == 0
     ref_words, ref_offs, tb = oracle.encode(x, ref, chunk)
     nw = (tb + 31) // 32
-    assert np.array_equal(offs, ref_offs)
-    assert np.array_equal(words[:nw], ref_words[:nw])
-    assert np.all(words[nw:] == SENTINEL)  # nothing written past the stream
+    variants = [(nslabs, sh)] if nslabs else []
+    nb = (x.size + 4095) // 4096
+    for s in (slab_counts or [0, 1, min(3, nb), min(nb, 16384)]):
+        variants.append((s, None))
+    for s, part in variants:
+        words, offs, code = gpu_encode(x, book, chunk, r, nslabs=s, slab_hist=part)
+        assert code == 0
+        assert np.array_equal(offs, ref_offs), (s, part is not None)
+        assert np.array_equal(words[:nw], ref_words[:nw]), (s, part is not None)
+        assert np.all(words[nw:] == SENTINEL)  # nothing written past the stream
     return book, words, offs, tb
 
 
@@ -111,6 +138,16 @@ def test_histogram_parity(n, A, dtype, offset):
     rng = np.random.default_rng(n + A)
     x = np.clip(np.rint(rng.normal(A / 2, max(1.0, A / 16), size=n)), 0, A - 1).astype(dtype)
     assert np.array_equal(gpu_hist(x, A, offset), oracle.histogram(x, A))
+
+
+@pytest.mark.parametrize("n,nslabs", [(1, 1), (4097, 2), (1_000_003, 7), (1_000_003, 245), (3 << 20, 768)])
+def test_histogram_slab_counts(n, nslabs):
+    rng = np.random.default_rng(n)
+    x = np.clip(np.rint(rng.normal(512, 30, size=n)), 0, 1023).astype(np.uint16)
+    h, sh = gpu_hist(x, 1024, nslabs=nslabs)
+    assert np.array_equal(h, oracle.histogram(x, 1024))
+    for g, (lo, hi) in enumerate(slab_ranges(n, nslabs)):
+        assert np.array_equal(sh[g], oracle.histogram(x[lo:hi], 1024)), g
 
 
 def test_histogram_peaked_single_bin():
@@ -198,24 +235,33 @@ def test_encode_single_symbol_stream():
     assert tb == x.size
 
 
-def test_encode_long_codes_wide_path():
-    """Fibonacci weights give 39-bit codes: the lane accumulator path for
-    codes longer than 32 bits."""
-    f = _fib(40)
-    h = np.zeros(1024, np.uint32)
-    h[100:140] = f
-    rng = np.random.default_rng(9)
-    x = rng.choice(np.arange(100, 140), size=50_000, p=np.array(f, float) / sum(f)).astype(np.uint16)
-    x[:40] = np.arange(100, 140)  # every code appears
+def _fib_stream(nfib: int, base: int, seed: int) -> np.ndarray:
+    """Symbols base..base+nfib-1 with exactly F_1..F_nfib occurrences each,
+    shuffled: the deepest Huffman tree, codes of nfib-1 bits."""
+    counts = np.array(_fib(nfib), dtype=np.int64)
+    x = np.repeat(np.arange(base, base + nfib, dtype=np.uint16), counts)
+    np.random.default_rng(seed).shuffle(x)
+    return x
+
+
+@pytest.mark.parametrize("nfib,mode", [(30, "codebook from global memory, 29-bit codes"),
+                                       (33, "codebook from global memory, 32-bit codes"),
+                                       (34, "codes over 32 bits, bits ORed into the output")])
+def test_encode_long_codes(nfib, mode):
+    x = _fib_stream(nfib, 200, nfib)
     ref_h = oracle.histogram(x, 1024)
     ref = oracle.codebook(ref_h)
+    assert ref.lmax == nfib - 1
     book, code = gpu_book(ref_h)
     assert code == 0
     assert_book_equal(book, ref)
-    words, offs, code = gpu_encode(x, book, 1024)
-    assert code == 0
-    rw, ro, tb = oracle.encode(x, ref, 1024)
-    assert np.array_equal(offs, ro) and np.array_equal(words[: rw.size], rw)
+    rw, ro, tb = oracle.encode(x, ref, 4096)
+    for r in (2, 4, 6):
+        words, offs, code = gpu_encode(x, book, 4096, r)
+        assert code == 0, mode
+        assert np.array_equal(offs, ro), mode
+        assert np.array_equal(words[: rw.size], rw), mode
+        assert np.all(words[rw.size:] == SENTINEL)
 
 
 def test_encode_large_alphabet_global_table():
