@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
+    p.add_argument("--mode", choices=("pipeline", "copy"), default="pipeline",
+                   help="copy: only time a device-to-device copy of the input (bandwidth calibration)")
     return p.parse_args()
 
 
@@ -88,6 +90,24 @@ def main():
     sb = x.dtype.itemsize
     d = torch.from_numpy(x.view(np.int16) if sb == 2 else x).cuda()
     n = x.size
+
+    # calibration: a plain device-to-device copy of the same number of bytes
+    dst = torch.empty_like(d)
+    for _ in range(3):
+        dst.copy_(d)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ncopy = 10
+    c0.record()
+    for _ in range(ncopy):
+        dst.copy_(d)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.nbytes / (c0.elapsed_time(c1) / ncopy * 1e-3) / 1e9
+    log(f"device copy of {x.nbytes} bytes: {copy_gbs:.0f} GB/s (read + write)")
+    if args.mode == "copy":
+        print(json.dumps({"mode": "copy", "bytes": x.nbytes, "copy_gbs": round(copy_gbs, 1)}), flush=True)
+        return
+    del dst
 
     enc = hf.Encoder(n, A, args.chunk, args.reduce_log2)
     r_eff = args.reduce_log2 or 4
@@ -175,6 +195,7 @@ def main():
             "input_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 4),
             "e2e_algorithmic_frac_of_hbm_peak": round(e2e_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "stage_us": {s: round(stage_ms[s] * 1e3, 2) for s in stages},
+            "device_copy_gbs": round(copy_gbs, 1),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -79,7 +79,9 @@ size_t hf_workspace_bytes(uint64_t n, uint32_t alphabet, uint32_t chunk_symbols)
   const uint64_t nblocks = (n + hf::kSlabBlock - 1) / hf::kSlabBlock;
   const size_t enc = hf::encode_workspace_bytes((uint32_t)(nblocks > 0 ? nblocks : 1));
   const size_t cb = hf::codebook_workspace_bytes(alphabet);
-  const size_t need = enc > cb ? enc : cb;
+  const size_t hist = (size_t)hf::histogram_internal_slabs(n, alphabet, num_cus()) * alphabet * 4;
+  size_t need = enc > cb ? enc : cb;
+  if (hist > need) need = hist;
   return need < 256 ? 256 : need;
 }
 
@@ -126,8 +128,6 @@ hf_status hf_time_next_main_kernel(void* before_event, void* after_event) {
 hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
                        uint32_t* d_hist, uint32_t nslabs, uint32_t* d_slab_hist, void* d_ws,
                        size_t ws_bytes, uint32_t* d_status, void* stream) {
-  (void)d_ws;
-  (void)ws_bytes;
   const KernelTimer timer = take_timer();
   if (!valid_symbols(sym_bytes, alphabet, n) || !d_hist || !d_status || (n > 0 && !d_sym))
     return HF_ERR_ARG;
@@ -135,8 +135,10 @@ hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32
   if (d_slab_hist && (nslabs == 0 || nslabs > blocks_of(n) || nslabs > hf::kMaxSlabs ||
                       alphabet > hf::kSlabHistMaxAlphabet))
     return HF_ERR_ARG;
+  if (d_ws && ((uintptr_t)d_ws & 255)) return HF_ERR_WORKSPACE;
   return launch_result(hf::launch_histogram(d_sym, n, sym_bytes, alphabet, d_hist, nslabs, d_slab_hist,
-                                            d_status, num_cus(), (hipStream_t)stream, timer));
+                                            (uint32_t*)d_ws, d_ws ? ws_bytes : 0, d_status, num_cus(),
+                                            (hipStream_t)stream, timer));
 }
 
 hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,

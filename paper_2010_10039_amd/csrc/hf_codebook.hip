@@ -1,7 +1,8 @@
 // hf_codebook.hip -- stages 2 and 3: parallel Huffman code lengths and
 // canonical codewords (Sec. 4.2, Algorithm 1 of the paper).
 //
-// One workgroup of 1024 lanes builds the whole book.  The paper runs its
+// One workgroup (256 lanes up to 4096 symbols, else 1024) builds the whole
+// book.  The paper runs its
 // construction as cooperative grid-wide kernels over global memory; a
 // codebook of a few thousand used symbols fits one gfx950 workgroup's LDS
 // (160 KiB), where a barrier costs ~100 cycles instead of a grid sync, so the
@@ -11,15 +12,18 @@
 // Steps:
 //  1. compaction: used symbols in ascending symbol order get compact index u;
 //     unused symbols receive cl = cw = 0 at once;
-//  2. sort leaves by (count, u) -- u preserves symbol order -- with a bitonic
-//     network on 48-bit keys (count << 16 | u); the paper sorts with Thrust;
+//  2. sort leaves by (count, u) -- u preserves symbol order -- on 48-bit keys
+//     (count << 16 | u): rank sort up to 512 used symbols, bitonic network
+//     above; the paper sorts with Thrust;
 //  3. GenerateCL: rounds of the parallel two-queue construction.  t = sum of
 //     the two lightest available nodes (leaf before internal on equal
 //     weight); every unconsumed leaf with weight <= t and every queued
 //     internal node are merged by key (Merge Path: each element's output
 //     position is its own index plus a binary search in the other run);
 //     consecutive pairs meld into new internal nodes; an odd last node waits
-//     for the next round.  This consumes nodes in exactly the order of a heap
+//     for the next round.  Every lane keeps the queue cursors and computes t
+//     itself from broadcast LDS reads, so a round costs three barriers and
+//     no single-lane section.  This consumes nodes in exactly the order of a heap
 //     keyed (weight, leaf-first, rank), so the lengths equal that heap's.
 //     The paper's strict "< t" threshold and its leader-pointer updates are
 //     replaced by "<= t" and one parent link per node;
@@ -86,14 +90,16 @@ struct Tree {
   IdT* nB;
 };
 
+constexpr int kCbMaxWaves = 16;
+
 struct Shared {
-  uint32_t wtot[kCbWaves];
+  uint32_t wtot[kCbMaxWaves];
   uint32_t cnt[kMaxLen + 1];
-  uint32_t cntw[kCbWaves][kMaxLen + 1];
+  uint32_t cntw[kCbMaxWaves][kMaxLen + 1];
   uint64_t first[kMaxLen + 1];
   uint32_t entry[kMaxLen + 1];
   uint64_t total;
-  uint32_t lc, ih, it, a, b, done;
+  uint32_t a;
   uint32_t lmax, lmin;
 };
 
@@ -110,12 +116,12 @@ __device__ __forceinline__ void count_lengths(uint32_t l, bool valid, uint32_t* 
   }
 }
 
-template <typename IdT>
+template <typename IdT, int NT>
 __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
                                            uint32_t A, uint32_t s_lo, uint32_t s_hi, uint32_t base,
                                            uint32_t m, const hf_codebook& book, uint32_t* status) {
+  constexpr int NW = NT / kWave;
   const uint32_t tid = threadIdx.x;
-  const uint32_t bd = kCbThreads;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
 
@@ -135,8 +141,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     }
   }
   const uint32_t P = pow2_ceil(m > 0 ? m : 1);
-  for (uint32_t i = m + tid; i < P; i += bd) t.key[i] = ~0ull;
-  for (uint32_t l = tid; l <= kMaxLen; l += bd) sh.cnt[l] = 0;
+  for (uint32_t l = tid; l <= kMaxLen; l += NT) sh.cnt[l] = 0;
   if (tid == 0) {
     sh.total = 0;
     sh.lmax = 0;
@@ -146,7 +151,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
 
   if (m <= 1) {
     // no tree: an empty book, or one symbol with the 1-bit code 0
-    for (uint32_t l = tid; l <= kMaxLen; l += bd) {
+    for (uint32_t l = tid; l <= kMaxLen; l += NT) {
       book.first[l] = 0;
       book.entry[l] = (m == 1 && l >= 2) ? 1u : 0u;
     }
@@ -167,65 +172,66 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     return;
   }
 
-  // ---- 2. bitonic sort of key[0, P) ascending ------------------------------
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tid; i < P / 2; i += bd) {
-        const uint32_t l = 2 * j * (i / j) + (i & (j - 1));
-        const uint32_t r = l + j;
-        const bool up = (l & k) == 0;
-        const uint64_t x = t.key[l], y = t.key[r];
-        if ((x > y) == up) {
-          t.key[l] = y;
-          t.key[r] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  // ---- 3. GenerateCL rounds ------------------------------------------------
-  if (tid == 0) {
-    sh.lc = 0;
-    sh.ih = 0;
-    sh.it = 0;
-  }
-  __syncthreads();
-  for (uint32_t round = 0;; ++round) {
-    if (tid == 0) {
-      const uint32_t lc = sh.lc, ih = sh.ih, it = sh.it;
-      if ((m - lc) + (it - ih) <= 1) {
-        sh.done = 1;
-      } else if (round >= m) {
-        // every round creates at least one node, so m - 1 rounds suffice
-        raise_status(status, HF_ERR_INTERNAL);
-        sh.done = 1;
-      } else {
-        // the two lightest available nodes, leaf first on equal weight
-        uint32_t li = lc, ii = ih;
-        uint64_t wsum = 0;
-        for (int p = 0; p < 2; ++p) {
-          const bool leaf = li < m && (ii >= it || (t.key[li] >> 16) <= t.iw[ii]);
-          wsum += leaf ? (t.key[li++] >> 16) : t.iw[ii++];
-        }
-        // leaves with weight <= t: upper bound in the sorted run [lc, m)
-        uint32_t lo = lc, hi = m;
-        while (lo < hi) {
-          const uint32_t md = (lo + hi) >> 1;
-          if ((t.key[md] >> 16) <= wsum) lo = md + 1;
-          else hi = md;
-        }
-        sh.a = lo - lc;
-        sh.b = it - ih;
-        sh.done = 0;
-      }
+  // ---- 2. sort leaves ascending by (count, u) --------------------------------
+  if (m <= 512) {
+    // rank sort: keys are distinct (u in the low bits); broadcast reads
+    for (uint32_t i = tid; i < m; i += NT) {
+      const uint64_t k = t.key[i];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < m; ++j) r += t.key[j] < k;
+      t.mw[r] = k;
     }
     __syncthreads();
-    if (sh.done) break;
-    const uint32_t lc = sh.lc, ih = sh.ih, it = sh.it, a = sh.a, b = sh.b;
+    for (uint32_t i = tid; i < m; i += NT) t.key[i] = t.mw[i];
+  } else {
+    for (uint32_t i = m + tid; i < P; i += NT) t.key[i] = ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = tid; i < P / 2; i += NT) {
+          const uint32_t l = 2 * j * (i / j) + (i & (j - 1));
+          const uint32_t r = l + j;
+          const bool up = (l & k) == 0;
+          const uint64_t x = t.key[l], y = t.key[r];
+          if ((x > y) == up) {
+            t.key[l] = y;
+            t.key[r] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. GenerateCL rounds ------------------------------------------------
+  // every lane tracks the queues: leaves [lc, m), internal nodes [ih, it)
+  uint32_t lc = 0, ih = 0, it = 0;
+  for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
+    if (round >= m) {  // every round creates at least one node: m - 1 rounds suffice
+      if (tid == 0) raise_status(status, HF_ERR_INTERNAL);
+      break;
+    }
+    // t = the two lightest available nodes, leaf first on equal weight
+    uint64_t wsum = 0;
+    {
+      uint32_t li = lc, ii = ih;
+      for (int p = 0; p < 2; ++p) {
+        const bool leaf = li < m && (ii >= it || (t.key[li] >> 16) <= t.iw[ii]);
+        wsum += leaf ? (t.key[li++] >> 16) : t.iw[ii++];
+      }
+    }
+    // a = leaves in [lc, m) with weight <= t: the lane seeing the boundary records it
+    for (uint32_t p = lc + tid; p <= m; p += NT) {
+      const bool below = p == lc || (t.key[p - 1] >> 16) <= wsum;
+      const bool above = p == m || (t.key[p] >> 16) > wsum;
+      if (below && above) sh.a = p - lc;
+    }
+    __syncthreads();
+    const uint32_t a = sh.a, b = it - ih;
     const uint32_t total = a + b, pairs = total >> 1;
     // Merge Path: leaves precede internal nodes of equal weight
-    for (uint32_t j = tid; j < a; j += bd) {
+    for (uint32_t j = tid; j < a; j += NT) {
       const uint64_t w = t.key[lc + j] >> 16;
       uint32_t lo = ih, hi = it;
       while (lo < hi) {
@@ -237,7 +243,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
       t.mw[pos] = w;
       t.mid[pos] = (IdT)(lc + j);
     }
-    for (uint32_t q = tid; q < b; q += bd) {
+    for (uint32_t q = tid; q < b; q += NT) {
       const uint64_t w = t.iw[ih + q];
       uint32_t lo = lc, hi = lc + a;
       while (lo < hi) {
@@ -250,29 +256,24 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
       t.mid[pos] = (IdT)(m + ih + q);
     }
     __syncthreads();
-    // Meld consecutive pairs
-    for (uint32_t p = tid; p < pairs; p += bd) {
+    // Meld consecutive pairs; an odd last node stays in its queue
+    for (uint32_t p = tid; p < pairs; p += NT) {
       const uint32_t k = it + p;
       t.iw[k] = t.mw[2 * p] + t.mw[2 * p + 1];
       t.par[t.mid[2 * p]] = (IdT)k;
       t.par[t.mid[2 * p + 1]] = (IdT)k;
     }
-    if (tid == 0) {
-      uint32_t lcn = lc + a, ihn = ih + b;
-      if (total & 1) {
-        if ((uint32_t)t.mid[total - 1] < m) lcn -= 1;
-        else ihn -= 1;
-      }
-      sh.lc = lcn;
-      sh.ih = ihn;
-      sh.it = it + pairs;
-    }
+    const bool carry_leaf = (total & 1) && (uint32_t)t.mid[total - 1] < m;
+    const bool carry_int = (total & 1) && !carry_leaf;
+    lc += a - (carry_leaf ? 1u : 0u);
+    ih += b - (carry_int ? 1u : 0u);
+    it += pairs;
     __syncthreads();
   }
 
   // ---- 4. depths by pointer jumping ----------------------------------------
   const uint32_t nint = m - 1, root = m - 2;
-  for (uint32_t k = tid; k < nint; k += bd) {
+  for (uint32_t k = tid; k < nint; k += NT) {
     t.dA[k] = (k == root) ? 0 : 1;
     t.nA[k] = (IdT)((k == root) ? root : (uint32_t)t.par[m + k]);
   }
@@ -283,7 +284,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   IdT* nn = t.nB;
   for (int step = 0;; ++step) {
     int active = 0;
-    for (uint32_t k = tid; k < nint; k += bd) {
+    for (uint32_t k = tid; k < nint; k += NT) {
       const IdT x = nc[k];
       const uint32_t d = (uint32_t)dc[k] + dc[x];
       dn[k] = (uint16_t)(d < 0xFFFFu ? d : 0xFFFFu);
@@ -303,7 +304,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   // ---- 5a. leaf lengths, counts per length, total bits ----------------------
   uint64_t bits = 0;
   uint32_t my_max = 0, my_min = 0xFFFFFFFFu;
-  for (uint32_t i0 = 0; i0 < m; i0 += bd) {
+  for (uint32_t i0 = 0; i0 < m; i0 += NT) {
     const uint32_t i = i0 + tid;
     const bool valid = i < m;
     uint32_t l = 0;
@@ -329,33 +330,36 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   if (my_min != 0xFFFFFFFFu) atomicMin(&sh.lmin, my_min);
   __syncthreads();
 
-  // ---- 5b. First and Entry ------------------------------------------------
-  if (tid == 0) {
-    uint32_t L = sh.lmax;
-    if (L > kMaxLen) {
-      raise_status(status, HF_ERR_CODELEN);
-      L = kMaxLen;
+  // ---- 5b. First and Entry (wave 0; lane j holds length j + 1) ----------------
+  if (wave == 0) {
+    const uint32_t L = sh.lmax > kMaxLen ? kMaxLen : sh.lmax;
+    const uint32_t c = sh.cnt[lane + 1];
+    const uint32_t below = wave_inclusive_scan(c) - c;  // codes shorter than lane + 1
+    uint64_t f = 0, mine = 0;
+    for (int l = (int)L - 1; l >= 1; --l) {
+      f = (f + (uint32_t)__builtin_amdgcn_readlane((int)c, l) + 1) >> 1;  // cnt[l + 1]
+      if ((int)lane == l - 1) mine = f;
     }
-    for (uint32_t l = 0; l <= kMaxLen; ++l) sh.first[l] = 0;
-    for (int l = (int)L - 1; l >= 1; --l) sh.first[l] = (sh.first[l + 1] + sh.cnt[l + 1] + 1) >> 1;
-    uint32_t below = 0;
-    for (uint32_t l = 0; l <= kMaxLen; ++l) {
-      sh.entry[l] = below;
-      if (l >= 1) below += sh.cnt[l];
+    sh.first[lane + 1] = mine;
+    sh.entry[lane + 1] = below;
+    if (lane == 0) {
+      sh.first[0] = 0;
+      sh.entry[0] = 0;
+      if (sh.lmax > kMaxLen) raise_status(status, HF_ERR_CODELEN);
+      book.info[0] = m;
+      book.info[1] = sh.lmax;
+      book.info[2] = sh.total;
+      book.info[3] = sh.lmin;
     }
-    book.info[0] = m;
-    book.info[1] = sh.lmax;
-    book.info[2] = sh.total;
-    book.info[3] = sh.lmin;
   }
   __syncthreads();
-  for (uint32_t l = tid; l <= kMaxLen; l += bd) {
+  for (uint32_t l = tid; l <= kMaxLen; l += NT) {
     book.first[l] = sh.first[l];
     book.entry[l] = sh.entry[l];
   }
 
   // ---- 5c. rank within each length in symbol order -------------------------
-  const uint32_t seg = ((m + kCbThreads - 1) / kCbThreads) * kWave;
+  const uint32_t seg = ((m + NT - 1) / NT) * kWave;
   const uint32_t sbeg = min(m, wave * seg), send = min(m, sbeg + seg);
   uint32_t creg = 0;  // lane l-1 counts length l
   for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
@@ -375,7 +379,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   __syncthreads();
   if (tid >= 1 && tid <= kMaxLen) {
     uint32_t run = sh.entry[tid];
-    for (int w = 0; w < kCbWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
       const uint32_t c = sh.cntw[w][tid];
       sh.cntw[w][tid] = run;
       run += c;
@@ -407,9 +411,9 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
 
 }  // namespace
 
-__global__ __launch_bounds__(kCbThreads) void codebook_kernel(const uint32_t* __restrict__ hist,
-                                                              hf_codebook book, char* ws,
-                                                              uint32_t* status) {
+template <int NT>
+__global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict__ hist, hf_codebook book,
+                                                      char* ws, uint32_t* status) {
   __shared__ Shared sh;
   __shared__ uint64_t s_key[kCbLdsMaxUsed];
   __shared__ uint64_t s_iw[kCbLdsMaxUsed];
@@ -421,12 +425,12 @@ __global__ __launch_bounds__(kCbThreads) void codebook_kernel(const uint32_t* __
 
   const uint32_t A = book.alphabet;
   const uint32_t tid = threadIdx.x;
-  const uint32_t per = (A + kCbThreads - 1) / kCbThreads;
+  const uint32_t per = (A + NT - 1) / NT;
   const uint32_t s_lo = min(A, tid * per), s_hi = min(A, s_lo + per);
   uint32_t c = 0;
   for (uint32_t s = s_lo; s < s_hi; ++s) c += (hist[s] != 0);
   uint32_t m;
-  const uint32_t base = block_exclusive_scan<kCbWaves>(c, sh.wtot, &m);
+  const uint32_t base = block_exclusive_scan<NT / kWave>(c, sh.wtot, &m);
 
   if (m <= kCbLdsMaxUsed) {
     Tree<uint16_t> t;
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(kCbThreads) void codebook_kernel(const uint32_t* __
     t.dB = t.dA + kCbLdsMaxUsed;
     t.nA = t.dB + kCbLdsMaxUsed;
     t.nB = t.nA + kCbLdsMaxUsed;
-    build_book(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+    build_book<uint16_t, NT>(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
   } else {
     const GlobalLayout L = global_layout(A);
     Tree<uint32_t> t;
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(kCbThreads) void codebook_kernel(const uint32_t* __
     t.dB = (uint16_t*)(ws + L.dB);
     t.nA = (uint32_t*)(ws + L.nA);
     t.nB = (uint32_t*)(ws + L.nB);
-    build_book(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+    build_book<uint32_t, NT>(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
   }
 }
 
@@ -468,7 +472,10 @@ hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* 
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
   (void)ws_bytes;
   timer.before(stream);
-  codebook_kernel<<<1, kCbThreads, 0, stream>>>(hist, book, (char*)ws, status);
+  if (book.alphabet <= kCbLdsMaxUsed)
+    codebook_kernel<256><<<1, 256, 0, stream>>>(hist, book, (char*)ws, status);
+  else
+    codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, (char*)ws, status);
   hipError_t e = hipGetLastError();
   timer.after(stream);
   return e;

@@ -234,7 +234,7 @@ struct EncShared {
 
 template <int R, int SB, int MODE>
 __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* tab, uint32_t* buf,
-                                            EncShared& sh, uint32_t g, uint64_t G) {
+                                            uint32_t* dummy, EncShared& sh, uint32_t g, uint64_t G) {
   constexpr uint32_t NS = 1u << R;
   constexpr uint32_t T = kEncThreads * NS;
   const uint32_t tid = threadIdx.x;
@@ -256,24 +256,38 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     uint32_t ent[NS];
     uint32_t L = 0;
     bool bad = false;
+    if (MODE == kModeTable && s_lo + (uint64_t)(t + 1) * T <= s_hi) {
+      // whole tile inside the slab: no per-symbol branches; tab[A] = 0 catches
+      // symbols outside the alphabet, a zero entry marks a symbol without code
+      uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
-    for (uint32_t i = 0; i < NS; ++i) {
-      const uint32_t sv = raw.symbol(i);
-      if (MODE == kModeTable) {
-        ent[i] = 0;
-        if (i < nvalid) {
-          const uint32_t e = sv < a.A ? tab[sv] : 0u;
-          bad |= e == 0;
-          ent[i] = e;
-          L += e & 31;
-        }
-      } else {
-        ent[i] = 0xFFFFFFFFu;
-        if (i < nvalid) {
-          const uint32_t l = sv < a.A ? a.cl[sv] : 0u;
-          bad |= l == 0;
-          if (l) ent[i] = sv;
-          L += l;
+      for (uint32_t i = 0; i < NS; ++i) {
+        const uint32_t e = tab[min(raw.symbol(i), a.A)];
+        ent[i] = e;
+        L += e & 31;
+        mn = min(mn, e);
+      }
+      bad = mn == 0;
+    } else {
+#pragma unroll
+      for (uint32_t i = 0; i < NS; ++i) {
+        const uint32_t sv = raw.symbol(i);
+        if (MODE == kModeTable) {
+          ent[i] = 0;
+          if (i < nvalid) {
+            const uint32_t e = tab[min(sv, a.A)];
+            bad |= e == 0;
+            ent[i] = e;
+            L += e & 31;
+          }
+        } else {
+          ent[i] = 0xFFFFFFFFu;
+          if (i < nvalid) {
+            const uint32_t l = sv < a.A ? a.cl[sv] : 0u;
+            bad |= l == 0;
+            if (l) ent[i] = sv;
+            L += l;
+          }
         }
       }
     }
@@ -285,18 +299,31 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     if (!last_tile) raw.load(a.sym, s0 + T, s_hi, a.vec_ok != 0);  // next tile, in flight meanwhile
 
     // ---- reduce-merge ---------------------------------------------------------
-    if (MODE != kModeWide) {
+    if (MODE == kModeTable) {
+      // at most one full word per code (<= 27 bits on <= 31 pending): the OR
+      // always issues, into this lane's dummy word when no word is complete
+      uint64_t acc = 0;
+      uint32_t nb = P & 31;  // pending bits, always < 32 between codes
+      uint32_t* wp = buf + (P >> 5);
+      uint32_t* const sink = dummy + tid;
+#pragma unroll
+      for (uint32_t i = 0; i < NS; ++i) {
+        const uint32_t len = ent[i] & 31;
+        acc = (acc << len) | (ent[i] >> 5);
+        nb += len;  // < 59
+        const bool full = nb >= 32;
+        nb &= 31;
+        atomicOr(full ? wp : sink, (uint32_t)(acc >> nb));
+        wp += full ? 1 : 0;
+      }
+      if (nb) atomicOr(wp, (uint32_t)(acc << (32 - nb)));
+    } else if (MODE == kModeGlobal) {
       uint64_t acc = 0;
       uint32_t nb = P & 31;
       uint64_t wi = P >> 5;
 #pragma unroll
-      for (uint32_t i = 0; i < NS; ++i) {
-        if (MODE == kModeTable) {
-          push_bits(acc, nb, wi, buf, ~0ull, ent[i] >> 5, ent[i] & 31);
-        } else if (ent[i] != 0xFFFFFFFFu) {
-          push_bits(acc, nb, wi, buf, ~0ull, (uint32_t)a.cw[ent[i]], a.cl[ent[i]]);
-        }
-      }
+      for (uint32_t i = 0; i < NS; ++i)
+        if (ent[i] != 0xFFFFFFFFu) push_bits(acc, nb, wi, buf, ~0ull, (uint32_t)a.cw[ent[i]], a.cl[ent[i]]);
       if (nb) atomicOr(&buf[wi], (uint32_t)(acc << (32 - nb)));
     } else if (P + L > (B > 32 ? B - 32 : 0u)) {
       // lanes holding the tile's last 32 bits build its tail record
@@ -400,11 +427,13 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   const uint32_t lmax = (uint32_t)a.info[1];
   const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
   const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  uint32_t* tab = lds;
-  uint32_t* buf = lds + (a.A <= kTableMaxAlphabet ? a.A : 0u);
+  // LDS: [tile buffer: T + 2 words][table: A + 1 entries, if A <= 8192][kEncThreads dummy words]
+  uint32_t* buf = lds;
+  uint32_t* tab = lds + T + 2;
+  uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
   if (mode == kModeTable)
-    for (uint32_t s = tid; s < a.A; s += kEncThreads) {
-      const uint32_t l = a.cl[s];
+    for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
+      const uint32_t l = s < a.A ? a.cl[s] : 0u;
       tab[s] = l ? (((uint32_t)a.cw[s]) << 5) | l : 0u;
     }
   if (mode != kModeWide)
@@ -422,9 +451,9 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   G = 0;
 #pragma unroll
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
-  if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, sh, g, G);
-  else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, sh, g, G);
-  else encode_slab<R, SB, kModeWide>(a, tab, buf, sh, g, G);
+  if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, dummy, sh, g, G);
+  else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
+  else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G);
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -449,7 +478,7 @@ EncodeFn pick(uint32_t r, uint32_t sb) {
 
 size_t encode_lds_bytes(uint32_t A, uint32_t r) {
   const size_t T = (size_t)kEncThreads << r;
-  return 4 * ((A <= kTableMaxAlphabet ? (size_t)A : 0) + T + 2);
+  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 2);
 }
 
 // Resident workgroups per CU, cached per kernel and LDS size.

@@ -93,6 +93,9 @@ __device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict
 // slabs [w*S/G, (w+1)*S/G); with slab_hist it stores each slab's counts
 // (differences of the running LDS totals, so the LDS is never cleared in
 // between) and, at the end, adds its totals to the global histogram.
+// With slab_hist the global histogram is left to hist_reduce_kernel (this
+// launch only zeroes it, from workgroup 0); otherwise every workgroup adds
+// its totals to it with one atomic per non-zero bin.
 template <int SB>
 __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
     const void* __restrict__ sym, uint64_t n, uint32_t A, uint32_t lo, uint32_t W, uint32_t R,
@@ -101,6 +104,8 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
   extern __shared__ uint32_t sub[];
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < W * R; i += blockDim.x) sub[i] = 0;
+  if (slab_hist && blockIdx.x == 0)
+    for (uint32_t b = tid; b < A; b += blockDim.x) hist[b] = 0;
   __syncthreads();
 
   const uint32_t rep = tid & (R - 1);
@@ -129,14 +134,32 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
       __syncthreads();
     }
   }
-  __syncthreads();
-
-  for (uint32_t b = tid; b < W; b += blockDim.x) {
-    uint32_t c = 0;
-    for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
-    if (c) atomicAdd(&hist[lo + b], c);
+  if (!slab_hist) {
+    __syncthreads();
+    for (uint32_t b = tid; b < W; b += blockDim.x) {
+      uint32_t c = 0;
+      for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+      if (c) atomicAdd(&hist[lo + b], c);
+    }
   }
   if (bad) raise_status(status, HF_ERR_SYMBOL);
+}
+
+// hist[b] += sum of rows [r0, r0 + kReduceRows) of the per-slab counts:
+// coalesced row reads, one atomic per non-zero bin and workgroup.
+constexpr uint32_t kReduceRows = 16;
+
+__global__ __launch_bounds__(kHistThreads) void hist_reduce_kernel(const uint32_t* __restrict__ part,
+                                                                   uint32_t nrows, uint32_t A,
+                                                                   uint32_t* __restrict__ hist) {
+  const uint32_t r0 = blockIdx.x * kReduceRows;
+  const uint32_t r1 = min(nrows, r0 + kReduceRows);
+  for (uint32_t b = threadIdx.x; b < A; b += blockDim.x) {
+    uint32_t c = 0;
+#pragma unroll 8
+    for (uint32_t r = r0; r < r1; ++r) c += part[(uint64_t)r * A + b];
+    if (c) atomicAdd(&hist[b], c);
+  }
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream) {
@@ -153,11 +176,11 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStrea
   return hipGetLastError();
 }
 
-// LDS per workgroup: up to 64 KiB for the replicated window (two
-// workgroups of 16 waves per CU); alphabets whose single replica needs more
-// use windows of up to 32768 bins (128 KiB, one workgroup per CU).
+// LDS per workgroup: 16 KiB of replicated window (eight 4-wave workgroups
+// per CU); alphabets whose single copy needs more use one copy of up to
+// 32768 bins (128 KiB) and several passes for larger alphabets.
 static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
-  const uint32_t budget = 64u << 10;
+  const uint32_t budget = 16u << 10;
   if (A * 4u <= budget) {
     uint32_t r = 1;
     while (r < 16 && A * 4u * (r * 2) <= budget) r *= 2;
@@ -169,23 +192,39 @@ static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
   }
 }
 
+uint32_t histogram_internal_slabs(uint64_t n, uint32_t alphabet, int num_cus) {
+  if (alphabet > kSlabHistMaxAlphabet) return 0;
+  const uint64_t nblocks = (n + kSlabBlock - 1) / kSlabBlock;
+  uint64_t s = std::min<uint64_t>((uint64_t)num_cus * 8, (nblocks + 3) / 4);
+  if (s > kMaxInternalSlabs) s = kMaxInternalSlabs;
+  return (uint32_t)(s > 0 ? s : 1);
+}
+
 hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t A,
-                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* status,
-                            int num_cus, hipStream_t stream, const KernelTimer& timer) {
-  hipError_t e = launch_fill_u32(hist, A, 0u, stream);
-  if (e != hipSuccess) return e;
+                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* ws,
+                            size_t ws_bytes, uint32_t* status, int num_cus, hipStream_t stream,
+                            const KernelTimer& timer) {
   uint32_t W, R;
   hist_plan(A, &W, &R);
   const size_t lds = (size_t)W * R * sizeof(uint32_t);
   const uint64_t nblocks = (n + kSlabBlock - 1) / kSlabBlock;
-  const uint32_t wgs_per_cu = (lds <= (64u << 10)) ? 2u : 1u;
-  uint64_t grid = (uint64_t)num_cus * wgs_per_cu;
+  hipError_t e;
+  if (!slab_hist && A <= kSlabHistMaxAlphabet) {
+    // per-slab counts into the workspace when it has room
+    const uint32_t s = histogram_internal_slabs(n, A, num_cus);
+    if (ws && (size_t)s * A * sizeof(uint32_t) <= ws_bytes) {
+      slab_hist = ws;
+      nslabs = s;
+    }
+  }
+  uint64_t grid;
   if (slab_hist) {
-    if (grid > nslabs) grid = nslabs;
+    grid = nslabs;  // one slab per workgroup
   } else {
-    // no per-slab output: one slab of at least 4 blocks per workgroup
-    const uint64_t want = (nblocks + 3) / 4;
-    if (grid > want) grid = want;
+    e = launch_fill_u32(hist, A, 0u, stream);
+    if (e != hipSuccess) return e;
+    const uint64_t wgs_per_cu = lds <= (16u << 10) ? 8 : (lds <= (64u << 10) ? 2 : 1);
+    grid = std::min<uint64_t>((uint64_t)num_cus * wgs_per_cu, (nblocks + 3) / 4);
     if (grid < 1) grid = 1;
     nslabs = (uint32_t)grid;
   }
@@ -206,6 +245,12 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
     if (e != hipSuccess) return e;
   }
   timer.after(stream);
+  if (slab_hist) {
+    hist_reduce_kernel<<<(nslabs + kReduceRows - 1) / kReduceRows, kHistThreads, 0, stream>>>(slab_hist, nslabs, A,
+                                                                                              hist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -8,9 +8,7 @@
 
 namespace hf {
 
-constexpr int kHistThreads = 1024;
-constexpr int kCbThreads = 1024;
-constexpr int kCbWaves = kCbThreads / 64;
+constexpr int kHistThreads = 256;
 constexpr uint32_t kCbLdsMaxUsed = 4096;  // codebook tree kept in LDS up to this many used symbols
 constexpr int kEncThreads = 256;
 constexpr int kEncWaves = kEncThreads / 64;
@@ -24,6 +22,7 @@ constexpr uint32_t kPackedMaxLen = 27;        // cw << 5 | cl fits 32 bits
 constexpr uint64_t kSlabBlock = 4096;
 constexpr uint32_t kSlabHistMaxAlphabet = 4096;  // per-slab counts kept up to this alphabet
 constexpr uint32_t kMaxSlabs = 16384;  // each encoder workgroup sums all earlier slab totals
+constexpr uint32_t kMaxInternalSlabs = 2048;  // per-slab counts the histogram keeps in the workspace
 
 __host__ __device__ inline uint64_t slab_begin(uint64_t g, uint64_t nblocks, uint64_t nslabs, uint64_t n) {
   const uint64_t s = (g * nblocks / nslabs) * kSlabBlock;
@@ -45,9 +44,14 @@ struct KernelTimer {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t stream);
 
+// Workgroups (= slabs) the histogram uses when the caller wants no per-slab
+// counts; the counts then go to the workspace (0 = large alphabet, atomics).
+uint32_t histogram_internal_slabs(uint64_t n, uint32_t alphabet, int num_cus);
+
 hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
-                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* status,
-                            int num_cus, hipStream_t stream, const KernelTimer& timer);
+                            uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist, uint32_t* ws,
+                            size_t ws_bytes, uint32_t* status, int num_cus, hipStream_t stream,
+                            const KernelTimer& timer);
 
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.

@@ -150,6 +150,23 @@ def test_histogram_slab_counts(n, nslabs):
         assert np.array_equal(sh[g], oracle.histogram(x[lo:hi], 1024)), g
 
 
+@pytest.mark.parametrize("n,A,dtype", [(1, 16, np.uint16), (1_000_003, 1024, np.uint16),
+                                       (2_000_001, 256, np.uint8), (300_001, 4096, np.uint16),
+                                       (300_001, 8192, np.uint16)])
+def test_histogram_with_workspace(n, A, dtype):
+    """With a workspace (and no per-slab buffer of the caller's) the counts
+    per slab go to the workspace and are reduced there; above 4096 symbols
+    the global atomics path is used."""
+    rng = np.random.default_rng(n + A + 7)
+    x = np.clip(np.rint(rng.normal(A / 2, max(1.0, A / 20), size=n)), 0, A - 1).astype(dtype)
+    d = _dev(x)
+    ws = hf.new_workspace(n, A)
+    status = hf.new_status()
+    h = hf.hf_histogram(d, A, ws=ws, status=status)
+    assert hf.read_status(status) == 0
+    assert np.array_equal(h.cpu().numpy().view(np.uint32), oracle.histogram(x, A))
+
+
 def test_histogram_peaked_single_bin():
     x = np.full(3_000_017, 511, dtype=np.uint16)
     x[::1000] = 3
