@@ -39,8 +39,16 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
-    p.add_argument("--mode", choices=("pipeline", "copy"), default="pipeline",
-                   help="copy: only time a device-to-device copy of the input (bandwidth calibration)")
+    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve"), default="pipeline",
+                   help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
+                        "batch: 512 independent streams per step, batched vs one plain pass per stream; "
+                        "serve: a Poisson trace of requests, continuous batching vs one request at a time")
+    p.add_argument("--requests", type=int, default=200, help="serve mode: requests in the trace")
+    p.add_argument("--qps", type=float, default=2000.0, help="serve mode: mean arrival rate")
+    p.add_argument("--arena-gib", type=float, default=48.0, help="serve mode: HBM arena for outputs and state")
+    p.add_argument("--streams", type=int, default=512, help="batch mode: streams per step")
+    p.add_argument("--tuning", default=os.path.join(ROOT, "paper_2010_10039_amd", "tuning_mi355x.json"),
+                   help="batch mode: autotuner table (tuned on the device when the file is missing)")
     return p.parse_args()
 
 
@@ -69,12 +77,267 @@ def cpu_baseline(x: np.ndarray, A: int, chunk: int, budget_s: float):
     }
 
 
+def _timed(fn, steps: int):
+    """Runs fn() `steps` times between two events on the current stream;
+    returns ms per call."""
+    import torch
+
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for k in range(steps):
+        fn(k)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def run_batch(args):
+    """Batched workload: `args.streams` independent streams (sizes
+    log-uniform in [2^16, 2^26] symbols, u8 or u16, alphabets 256..8192,
+    discrete Gaussians with sigma log-uniform in [0.5, 50]), all encoded by
+    one hf_encode_batch call per step, next to the same streams encoded by
+    one plain hist -> codebook -> encode pass each, in turn."""
+    import torch
+
+    from paper_2010_10039_amd import autotune, hf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    syms, alph = workloads.batched_streams(args.streams, seed=1000, device="cuda")
+    torch.cuda.synchronize()
+    total_bytes = sum(t.numel() * t.element_size() for t in syms)
+    total_syms = sum(t.numel() for t in syms)
+    log(f"generated {len(syms)} streams: {total_syms} symbols, {total_bytes} bytes "
+        f"in {time.perf_counter() - t0:.1f}s")
+    if os.path.exists(args.tuning):
+        tuner = autotune.Autotuner.load(args.tuning)
+        log(f"autotuner table from {args.tuning}")
+    else:
+        t0 = time.perf_counter()
+        tuner = autotune.tune()
+        log(f"tuned on the device in {time.perf_counter() - t0:.1f}s")
+    sbs = [t.element_size() for t in syms]
+
+    # first pass: beta unknown, so the tuner's beta-independent choice
+    first = [tuner.choose(sb, A, None) for sb, A in zip(sbs, alph)]
+    enc = hf.BatchEncoder(syms, alph, [c.chunk for c in first], [c.r for c in first])
+    enc.run()
+    torch.cuda.synchronize()
+    hf.raise_on_status(enc.status.max().reshape(1), "batch pass")
+    infos = torch.stack([b.info for b in enc.books]).cpu().numpy().view(np.uint64)
+    betas = [int(infos[i, 2]) / max(1, t.numel()) for i, t in enumerate(syms)]
+    # later passes: each stream's beta is known from its device-resident book
+    picks = [tuner.choose(sb, A, b if t.numel() else None) for sb, A, b, t in zip(sbs, alph, betas, syms)]
+    del enc
+    enc = hf.BatchEncoder(syms, alph, [c.chunk for c in picks], [c.r for c in picks])
+    for _ in range(args.warmup):
+        enc.run()
+    torch.cuda.synchronize()
+    hf.raise_on_status(enc.status.max().reshape(1), "batch warmup")
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        b.record()
+
+    def batch_step(k):
+        hf.hf_time_next_main_kernel(*evs[k])
+        enc.run()
+
+    wall0 = time.perf_counter()
+    ms_batch = _timed(batch_step, args.steps)
+    wall = (time.perf_counter() - wall0) / args.steps
+    hf.raise_on_status(enc.status.max().reshape(1), "batch steps")
+    enc_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    log(f"batched: {ms_batch:.3f} ms/step (wall {wall * 1e3:.3f} ms), encode stage {enc_ms:.3f} ms")
+
+    # every stream decodes back to its input
+    bad = 0
+    for i, t in enumerate(syms):
+        if t.numel():
+            r = hf.hf_decode_check(enc.outs[i], enc.offsets[i], t, picks[i].chunk, enc.books[i])
+            bad += int(r[0].item())
+    if bad:
+        raise SystemExit(f"batched decode check failed: {bad} mismatching symbols")
+
+    # the same streams, one plain pass each (same chunk and r per stream)
+    plain = [hf.Encoder(t.numel(), A, c.chunk, c.r) for t, A, c in zip(syms, alph, picks) if t.numel()]
+    live = [t for t in syms if t.numel()]
+
+    def plain_step(k):
+        for e, t in zip(plain, live):
+            e.run(t)
+
+    for _ in range(max(1, args.warmup)):
+        plain_step(0)
+    psteps = max(2, args.steps // 4)
+    ms_plain = _timed(plain_step, psteps)
+    for e in plain:
+        hf.raise_on_status(e.status, "plain steps")
+    same = all(torch.equal(e.offsets, enc.offsets[i]) and
+               torch.equal(e.out[:(int(e.offsets[-1].item()) + 31) // 32],
+                           enc.outs[i][:(int(e.offsets[-1].item()) + 31) // 32])
+               for i, e in zip([i for i, t in enumerate(syms) if t.numel()], plain))
+    log(f"plain launches: {ms_plain:.3f} ms/step; outputs identical: {same}")
+    if not same:
+        raise SystemExit("batched and plain outputs differ")
+
+    value = total_bytes / (ms_batch * 1e-3) / 1e9
+    out_bytes = sum((int(infos[i, 2]) + 31) // 32 * 4 for i in range(len(syms)))
+    off_bytes = sum(((t.numel() + c.chunk - 1) // c.chunk + 1) * 8 for t, c in zip(syms, picks))
+    enc_bytes = total_bytes + out_bytes + off_bytes + sum(A * 9 for A in alph)
+    achieved = enc_bytes / (enc_ms * 1e-3) / 1e9
+    rs = {r: sum(1 for c in picks if c.r == r) for r in autotune.R_CHOICES}
+    cs = {c: sum(1 for p in picks if p.chunk == c) for c in autotune.CHUNK_CHOICES}
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+
+        log("timing the CPU oracle on a sample of the streams")
+        done_bytes, spent, k = 0, 0.0, 0
+        while k < len(syms) and spent < args.cpu_seconds:
+            x = syms[k].cpu().numpy()
+            x = x.view(np.uint16) if x.dtype == np.int16 else x
+            t1 = time.perf_counter()
+            book = oracle.codebook(oracle.histogram(x, alph[k]))
+            oracle.encode(x, book, picks[k].chunk)
+            spent += time.perf_counter() - t1
+            done_bytes += x.nbytes
+            k += 1
+        cpu = {"value": round(done_bytes / spent / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"streams 0..{k - 1} of the batch ({done_bytes} bytes), one whole pass each, serial C"}
+    return {
+        "metric": "batched encode GB/s of input symbols",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batch, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8+u16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched_{len(syms)}_streams_64K_64M_mixed",
+            "streams": len(syms),
+            "total_symbols": total_syms,
+            "total_bytes": total_bytes,
+            "plain_launches_ms_per_step": round(ms_plain, 4),
+            "plain_launches_gbs": round(total_bytes / (ms_plain * 1e-3) / 1e9, 2),
+            "speedup_vs_plain_launches": round(ms_plain / ms_batch, 3),
+            "outputs_identical_to_plain": same,
+            "reduce_log2_counts": rs,
+            "chunk_counts": cs,
+            "input_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "batch_encode_kernel",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": enc_bytes,
+            "avg_launch_us": round(enc_ms * 1e3, 2),
+        },
+        "cpu_baseline": cpu,
+    }
+
+
+def run_serve(args):
+    """Served workload: a trace of `args.requests` requests with Poisson
+    arrivals at `args.qps` (sizes log-uniform in 1 MiB..512 MiB, u8 or u16,
+    alphabets 256..65536, skew-normal or Zipf), served in real time by the
+    continuous-batching loop and, on the same trace, by a server that runs
+    one request at a time with plain launches.  Inputs are in HBM before the
+    trace starts (as if produced there by an upstream stage)."""
+    import torch
+
+    from paper_2010_10039_amd import serve, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    trace = workloads.served_requests(args.requests, seed=2000, qps=args.qps, device="cuda")
+    torch.cuda.synchronize()
+    total = sum(x.numel() * x.element_size() for _, x, _, _ in trace)
+    log(f"generated {len(trace)} requests, {total} bytes, in {time.perf_counter() - t0:.1f}s; "
+        f"trace spans {trace[-1][0] * 1e3:.1f} ms")
+    cap = int(args.arena_gib * (1 << 30))
+
+    def make():
+        return [serve.Request(i, x.numel(), x.element_size(), A, t, chunk=args.chunk, sym=x)
+                for i, (t, x, A, _) in enumerate(trace)]
+
+    def stats(loop, reqs):
+        bad = [r.rid for r in reqs if r.status != 0]
+        if bad:
+            raise SystemExit(f"served requests failed: {bad[:10]}")
+        lat = [r.latency * 1e3 for r in reqs]
+        span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+        return {"gbs": round(total / span / 1e9, 2), "p50_ms": round(serve.percentile(lat, 50), 3),
+                "p99_ms": round(serve.percentile(lat, 99), 3), "mean_ms": round(sum(lat) / len(lat), 3),
+                "span_ms": round(span * 1e3, 2), "batches": loop.batches, "max_batch": loop.max_batch_seen,
+                "max_concurrent_batches": loop.max_busy}
+
+    # warm up both servers on a short prefix (kernels, allocator, staging)
+    for kw in (dict(slots=3, max_batch=32), dict(slots=1, max_batch=1, use_batch=False)):
+        serve.serve(make()[:8], cap, **kw)
+    torch.cuda.synchronize()
+    res = {}
+    for name, kw in (("continuous_batching", dict(slots=3, max_batch=32)),
+                     ("plain_one_at_a_time", dict(slots=1, max_batch=1, use_batch=False))):
+        reqs = make()
+        loop = serve.serve(reqs, cap, **kw)
+        torch.cuda.synchronize()
+        res[name] = stats(loop, reqs)
+        log(f"{name}: {res[name]}")
+    cb, pl = res["continuous_batching"], res["plain_one_at_a_time"]
+    return {
+        "metric": "served encode GB/s of input symbols, p50/p99 latency",
+        "value": cb["gbs"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": cb["span_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8+u16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"served_{len(trace)}_requests_1MiB_512MiB_qps{args.qps:g}",
+            "requests": len(trace),
+            "total_bytes": total,
+            "qps": args.qps,
+            "p50_ms": cb["p50_ms"],
+            "p99_ms": cb["p99_ms"],
+            "continuous_batching": cb,
+            "plain_one_at_a_time": pl,
+        },
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this encoder runs each stream on a single device); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.mode == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return
 
     import torch
 

@@ -178,10 +178,58 @@ hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_off
                           void* stream);
 
 /*
- * Profiling hook: for the next call of hf_histogram, hf_build_codebook or
- * hf_encode made by this host thread, record hipEvent_t `before`
- * immediately before that call's main kernel and `after` immediately after
- * it, on the call's stream.  Either may be NULL to clear the hook.  One-shot.
+ * Batched encoding of many independent streams, each with its own symbol
+ * width, alphabet and codebook (an extension beyond the paper, which
+ * encodes one stream at a time).  Every stream gets exactly what
+ * hf_histogram + hf_build_codebook + hf_encode would produce for it alone.
+ * All pointers in a descriptor are device memory owned by the caller;
+ * `book` is written.  hist may be NULL.  Limits per stream: n < 2^32,
+ * book.alphabet <= 8192 (<= 256 for sym_bytes 1), chunk_symbols a power of
+ * two in [256, 65536], reduce_log2 3, 4, 5 or 0 (the library default);
+ * reserved must be 0.  The output is bit-identical whatever the other
+ * streams of the batch are.
+ */
+typedef struct hf_stream_desc {
+  const void* sym;
+  uint64_t n;
+  uint32_t sym_bytes;
+  uint32_t chunk_symbols;
+  uint32_t reduce_log2;
+  uint32_t reserved;
+  uint32_t* hist;
+  hf_codebook book;
+  uint32_t* out;
+  uint64_t out_capacity_words;
+  uint64_t* chunk_bit_offsets;
+} hf_stream_desc;
+
+/* Workspace bytes hf_encode_batch needs for these descriptors (0 if one is
+ * invalid). */
+size_t hf_batch_workspace_bytes(const hf_stream_desc* descs, uint32_t nstreams);
+
+/*
+ * Encodes all streams with one launch per stage, whatever their number:
+ * per-slab histograms of every stream; one workgroup per stream that reduces
+ * them, builds the stream's book (as hf_build_codebook) and places its
+ * slabs; then every slab of every stream is encoded as hf_encode does.
+ * `descs` is a HOST array of nstreams descriptors; the plan derived from it
+ * is copied to the workspace through library-owned pinned host buffers
+ * (reused once their copy has completed) before the kernels run, so descs
+ * may be reused when the call returns.  Calls on different streams do not
+ * wait for each other.
+ * d_status is uint32[nstreams], caller-zeroed; stream s's device errors go
+ * to d_status[s].  Returns HF_ERR_ARG if any descriptor is invalid (nothing
+ * is launched).
+ */
+hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* d_ws, size_t ws_bytes,
+                          uint32_t* d_status, void* stream);
+
+/*
+ * Profiling hook: for the next call of hf_histogram, hf_build_codebook,
+ * hf_encode or hf_encode_batch made by this host thread, record hipEvent_t
+ * `before` immediately before that call's main kernel (for hf_encode_batch:
+ * its encoding launches) and `after` immediately after it, on the call's
+ * stream.  Either may be NULL to clear the hook.  One-shot.
  */
 hf_status hf_time_next_main_kernel(void* before_event, void* after_event);
 

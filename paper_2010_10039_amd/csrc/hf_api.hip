@@ -11,12 +11,7 @@ using hf::KernelTimer;
 
 thread_local KernelTimer t_timer;
 
-// Takes the armed one-shot timer (if any) for this call.
-KernelTimer take_timer() {
-  KernelTimer t = t_timer;
-  t_timer = KernelTimer{};
-  return t;
-}
+KernelTimer take_timer() { return hf::take_main_timer(); }
 
 int num_cus() {
   static std::mutex mu;
@@ -71,6 +66,14 @@ uint32_t default_slabs(uint64_t n, uint32_t alphabet, uint32_t sym_bytes) {
 }
 
 }  // namespace
+
+namespace hf {
+KernelTimer take_main_timer() {
+  KernelTimer t = t_timer;
+  t_timer = KernelTimer{};
+  return t;
+}
+}  // namespace hf
 
 extern "C" {
 

@@ -1,0 +1,233 @@
+// hf_batch.hip -- batched encoding of many independent streams: host
+// planning and the three stage launches (histogram of every slab of every
+// stream; one codebook per stream plus slab offsets; encoding of every
+// slab), whatever the number of streams.
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "hf_kernels.h"
+
+namespace {
+
+// Largest alphabet of a batched stream: its per-slab counts stay small and
+// its codes are looked up from an LDS table.
+constexpr uint32_t kBatchMaxAlphabet = 8192;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+uint32_t log2_exact(uint32_t x) {
+  uint32_t l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+// Slabs of a batched stream: at least 16 blocks (64 Ki symbols), and enough
+// symbols that the per-slab counts stay near 1/64 of the stream's bytes.
+uint32_t batch_slabs(uint64_t n, uint32_t sym_bytes, uint32_t alphabet) {
+  const uint64_t nblocks = (n + hf::kSlabBlock - 1) / hf::kSlabBlock;
+  if (nblocks == 0) return 0;
+  uint64_t per = ((uint64_t)alphabet * 4 * 64 / sym_bytes + hf::kSlabBlock - 1) / hf::kSlabBlock;
+  if (per < 16) per = 16;
+  uint64_t s = (nblocks + per - 1) / per;
+  if (s > nblocks) s = nblocks;
+  if (s > hf::kMaxSlabs) s = hf::kMaxSlabs;
+  return (uint32_t)(s > 0 ? s : 1);
+}
+
+uint32_t group_of(uint32_t r) { return r == 3 ? 0u : (r == 5 ? 2u : 1u); }
+
+struct Plan {
+  std::vector<hf::BatchStream> bs;
+  std::vector<uint32_t> item_stream;  // stream of every item
+  std::vector<uint32_t> items;        // items grouped by r (3, 4, 5)
+  uint32_t group_count[3] = {0, 0, 0};
+  uint32_t group_start[3] = {0, 0, 0};
+  uint32_t max_alphabet = 1;
+  size_t off_streams = 0, off_item_stream = 0, off_items = 0, header_bytes = 0, total_bytes = 0;
+};
+
+hf_status validate(const hf_stream_desc& d) {
+  const uint32_t A = d.book.alphabet;
+  if (d.sym_bytes != 1 && d.sym_bytes != 2) return HF_ERR_ARG;
+  if (A == 0 || A > kBatchMaxAlphabet || (d.sym_bytes == 1 && A > 256u)) return HF_ERR_ARG;
+  if (d.n >= (1ull << 32)) return HF_ERR_ARG;
+  if (!is_pow2(d.chunk_symbols) || d.chunk_symbols < 256u || d.chunk_symbols > 65536u) return HF_ERR_ARG;
+  if (d.reduce_log2 != 0 && (d.reduce_log2 < 3 || d.reduce_log2 > 5)) return HF_ERR_ARG;
+  if (d.reserved != 0) return HF_ERR_ARG;
+  if (!d.book.cl || !d.book.cw || !d.book.first || !d.book.entry || !d.book.rev || !d.book.info) return HF_ERR_ARG;
+  if (!d.chunk_bit_offsets) return HF_ERR_ARG;
+  if (d.n > 0 && (!d.sym || !d.out || ((uintptr_t)d.sym % d.sym_bytes) != 0)) return HF_ERR_ARG;
+  return HF_OK;
+}
+
+// Lays out the workspace (ws may be null to only size it).
+hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t* d_status, Plan& p) {
+  size_t o = 0;
+  p.off_streams = o;
+  o += align256(sizeof(hf::BatchStream) * ns);
+  uint64_t nitems = 0;
+  for (uint32_t s = 0; s < ns; ++s) {
+    const hf_status v = validate(descs[s]);
+    if (v != HF_OK) return v;
+    nitems += batch_slabs(descs[s].n, descs[s].sym_bytes, descs[s].book.alphabet);
+  }
+  if (nitems >= (1ull << 31)) return HF_ERR_ARG;
+  p.off_item_stream = o;
+  o += align256(4 * nitems);
+  p.off_items = o;
+  o += align256(4 * nitems);
+  p.header_bytes = o;
+  p.bs.resize(ns);
+  p.item_stream.clear();
+  p.item_stream.reserve(nitems);
+  std::vector<uint32_t> groups[3];
+  for (uint32_t s = 0; s < ns; ++s) {
+    const hf_stream_desc& d = descs[s];
+    hf::BatchStream& b = p.bs[s];
+    const uint32_t A = d.book.alphabet;
+    b.sym = d.sym;
+    b.n = d.n;
+    b.nblocks = (d.n + hf::kSlabBlock - 1) / hf::kSlabBlock;
+    b.sym_bytes = d.sym_bytes;
+    b.A = A;
+    b.nslabs = batch_slabs(d.n, d.sym_bytes, A);
+    b.item0 = (uint32_t)p.item_stream.size();
+    b.r = d.reduce_log2 ? d.reduce_log2 : (uint32_t)hf::kEncDefaultR;
+    b.chunk_log2 = log2_exact(d.chunk_symbols);
+    b.nchunks = (d.n + d.chunk_symbols - 1) / d.chunk_symbols;
+    b.book = d.book;
+    b.out = d.out;
+    b.cap_words = d.out_capacity_words;
+    b.offsets = d.chunk_bit_offsets;
+    b.status = d_status + s;
+    b.part = (uint32_t*)(ws + o);
+    o += align256((size_t)b.nslabs * A * 4);
+    if (d.hist) {
+      b.hist = d.hist;
+    } else {
+      b.hist = (uint32_t*)(ws + o);
+      o += align256((size_t)A * 4);
+    }
+    const size_t cb = hf::codebook_workspace_bytes(A);
+    b.cb_ws = cb ? ws + o : nullptr;
+    o += align256(cb);
+    b.slab_G = (uint64_t*)(ws + o);
+    o += align256((size_t)b.nslabs * 8);
+    b.slab_tail = (uint32_t*)(ws + o);
+    o += align256((size_t)b.nslabs * 4);
+    if (A > p.max_alphabet) p.max_alphabet = A;
+    for (uint32_t g = 0; g < b.nslabs; ++g) {
+      groups[group_of(b.r)].push_back((uint32_t)p.item_stream.size());
+      p.item_stream.push_back(s);
+    }
+  }
+  p.items.clear();
+  for (int k = 0; k < 3; ++k) {
+    p.group_start[k] = (uint32_t)p.items.size();
+    p.group_count[k] = (uint32_t)groups[k].size();
+    p.items.insert(p.items.end(), groups[k].begin(), groups[k].end());
+  }
+  p.total_bytes = o;
+  return HF_OK;
+}
+
+// Pinned staging buffers for plan uploads.  A buffer is reused once the
+// copy out of it has completed (its event has fired), so calls on different
+// streams never wait for each other's kernels; when every buffer is still
+// in use a new one is added, up to kMaxStages, after which the call waits
+// for the oldest.
+struct Stage {
+  char* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  uint64_t last_use = 0;
+};
+constexpr size_t kMaxStages = 64;
+std::mutex g_stage_mu;
+std::vector<Stage> g_stages;
+uint64_t g_stage_clock = 0;
+
+// Picks a free staging buffer of at least `bytes` (caller holds the lock).
+Stage* acquire_stage(size_t bytes) {
+  Stage* pick = nullptr;
+  for (Stage& s : g_stages)
+    if (hipEventQuery(s.done) == hipSuccess && (!pick || s.bytes > pick->bytes)) pick = &s;
+  if (!pick && g_stages.size() < kMaxStages) {
+    Stage s;
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return nullptr;
+    g_stages.push_back(s);
+    pick = &g_stages.back();
+  }
+  if (!pick) {
+    pick = &g_stages[0];
+    for (Stage& s : g_stages)
+      if (s.last_use < pick->last_use) pick = &s;
+    if (hipEventSynchronize(pick->done) != hipSuccess) return nullptr;
+  }
+  if (pick->bytes < bytes) {
+    if (pick->host) (void)hipHostFree(pick->host);
+    pick->host = nullptr;
+    pick->bytes = 0;
+    if (hipHostMalloc((void**)&pick->host, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    pick->bytes = bytes;
+  }
+  pick->last_use = ++g_stage_clock;
+  return pick;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hf_batch_workspace_bytes(const hf_stream_desc* descs, uint32_t nstreams) {
+  if (!descs || nstreams == 0) return 256;
+  Plan p;
+  static uint32_t dummy_status;
+  if (make_plan(descs, nstreams, nullptr, &dummy_status, p) != HF_OK) return 0;
+  return p.total_bytes;
+}
+
+hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* d_ws, size_t ws_bytes,
+                          uint32_t* d_status, void* stream) {
+  const hf::KernelTimer timer = hf::take_main_timer();
+  if (!descs || nstreams == 0 || !d_status) return HF_ERR_ARG;
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return HF_ERR_WORKSPACE;
+  Plan p;
+  const hf_status v = make_plan(descs, nstreams, (char*)d_ws, d_status, p);
+  if (v != HF_OK) return v;
+  if (ws_bytes < p.total_bytes) return HF_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)d_ws;
+  {
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    Stage* sg = acquire_stage(p.header_bytes);
+    if (!sg) return HF_ERR_LAUNCH;
+    memcpy(sg->host + p.off_streams, p.bs.data(), sizeof(hf::BatchStream) * nstreams);
+    memcpy(sg->host + p.off_item_stream, p.item_stream.data(), 4 * p.item_stream.size());
+    memcpy(sg->host + p.off_items, p.items.data(), 4 * p.items.size());
+    if (hipMemcpyAsync(ws, sg->host, p.header_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return HF_ERR_LAUNCH;
+    if (hipEventRecord(sg->done, st) != hipSuccess) return HF_ERR_LAUNCH;
+  }
+  const hf::BatchStream* d_streams = (const hf::BatchStream*)(ws + p.off_streams);
+  const uint32_t* d_item_stream = (const uint32_t*)(ws + p.off_item_stream);
+  const uint32_t* d_items = (const uint32_t*)(ws + p.off_items);
+  const uint32_t nitems = (uint32_t)p.item_stream.size();
+  if (hf::launch_batch_histogram(d_streams, d_item_stream, nitems, p.max_alphabet, st) != hipSuccess)
+    return HF_ERR_LAUNCH;
+  if (hf::launch_batch_codebook(d_streams, nstreams, st) != hipSuccess) return HF_ERR_LAUNCH;
+  timer.before(st);
+  const uint32_t rs[3] = {3, 4, 5};
+  for (int k = 0; k < 3; ++k) {
+    if (!p.group_count[k]) continue;
+    if (hf::launch_batch_encode(d_streams, d_item_stream, d_items + p.group_start[k], p.group_count[k], rs[k],
+                                p.max_alphabet, st) != hipSuccess)
+      return HF_ERR_LAUNCH;
+  }
+  timer.after(st);
+  return HF_OK;
+}
+
+}  // extern "C"

@@ -109,10 +109,120 @@ __device__ __forceinline__ void count_lengths(uint32_t l, bool valid, uint32_t* 
   uint64_t pending = __ballot(valid);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lv = __shfl(l, leader, kWave);
+    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
     const uint64_t mask = __ballot(valid && l == lv);
     if (lane_id() == leader) atomicAdd(&cnt[lv], (uint32_t)__popcll(mask));
     pending &= ~mask;
+  }
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders this wave's earlier memory writes before its later reads (the
+// single-wave rounds need no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// GenerateCL rounds run by one wave: the round's threshold, selection count,
+// carry and queue cursors are wave-uniform values obtained with readlane and
+// ballots, so a round needs no workgroup barrier.  Merge ranks for runs of
+// at most 64 nodes come from counting over register-broadcast weights.
+template <typename IdT>
+__device__ __forceinline__ void rounds_one_wave(const Tree<IdT>& t, uint32_t m, uint32_t* status) {
+  const uint32_t lane = lane_id();
+  uint32_t lc = 0, ih = 0, it = 0;
+  for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
+    if (round >= m) {  // every round creates at least one node: m - 1 rounds suffice
+      if (lane == 0) raise_status(status, HF_ERR_INTERNAL);
+      break;
+    }
+    // the two lightest nodes: lanes 0-1 read the leaf queue head, 2-3 the internal one
+    uint64_t hv = ~0ull;
+    if (lane < 2) {
+      if (lc + lane < m) hv = t.key[lc + lane] >> 16;
+    } else if (lane < 4) {
+      if (ih + lane - 2 < it) hv = t.iw[ih + lane - 2];
+    }
+    const uint64_t l0 = readlane64(hv, 0), l1 = readlane64(hv, 1);
+    const uint64_t i0 = readlane64(hv, 2), i1 = readlane64(hv, 3);
+    uint64_t w1, w2;  // leaf first on equal weight; ~0 marks an empty slot
+    if (l0 <= i0) {
+      w1 = l0;
+      w2 = l1 <= i0 ? l1 : i0;
+    } else {
+      w1 = i0;
+      w2 = l0 <= i1 ? l0 : i1;
+    }
+    const uint64_t tw = w1 + w2;
+    // a = leaves in [lc, m) no heavier than tw (a prefix of the sorted run)
+    uint32_t a = 0;
+    for (uint32_t base = lc; base < m; base += kWave) {
+      const uint32_t p = base + lane;
+      const uint32_t c = (uint32_t)__popcll(__ballot(p < m && (t.key[p] >> 16) <= tw));
+      a += c;
+      if (c < (uint32_t)kWave) break;
+    }
+    const uint32_t b = it - ih, total = a + b, pairs = total >> 1;
+    // merge by key: leaf j goes to j + #internals lighter than it, internal q
+    // to q + #leaves no heavier than it
+    if (a <= (uint32_t)kWave && b <= (uint32_t)kWave) {
+      const uint64_t wl = lane < a ? (t.key[lc + lane] >> 16) : ~0ull;
+      const uint64_t wi = lane < b ? t.iw[ih + lane] : ~0ull;
+      uint32_t rl = 0, ri = 0;
+      for (uint32_t q = 0; q < b; ++q) rl += readlane64(wi, (int)q) < wl;
+      for (uint32_t j = 0; j < a; ++j) ri += readlane64(wl, (int)j) <= wi;
+      if (lane < a) {
+        t.mw[lane + rl] = wl;
+        t.mid[lane + rl] = (IdT)(lc + lane);
+      }
+      if (lane < b) {
+        t.mw[lane + ri] = wi;
+        t.mid[lane + ri] = (IdT)(m + ih + lane);
+      }
+    } else {
+      for (uint32_t j = lane; j < a; j += kWave) {
+        const uint64_t w = t.key[lc + j] >> 16;
+        uint32_t lo = ih, hi = it;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if (t.iw[md] < w) lo = md + 1;
+          else hi = md;
+        }
+        t.mw[j + (lo - ih)] = w;
+        t.mid[j + (lo - ih)] = (IdT)(lc + j);
+      }
+      for (uint32_t q = lane; q < b; q += kWave) {
+        const uint64_t w = t.iw[ih + q];
+        uint32_t lo = lc, hi = lc + a;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if ((t.key[md] >> 16) <= w) lo = md + 1;
+          else hi = md;
+        }
+        t.mw[q + (lo - lc)] = w;
+        t.mid[q + (lo - lc)] = (IdT)(m + ih + q);
+      }
+    }
+    wave_sync();
+    // meld consecutive pairs; an odd last node stays in its queue
+    for (uint32_t p = lane; p < pairs; p += kWave) {
+      const uint32_t k = it + p;
+      t.iw[k] = t.mw[2 * p] + t.mw[2 * p + 1];
+      t.par[t.mid[2 * p]] = (IdT)k;
+      t.par[t.mid[2 * p + 1]] = (IdT)k;
+    }
+    const bool carry_leaf = (total & 1) && (uint32_t)t.mid[total - 1] < m;
+    const bool carry_int = (total & 1) && !carry_leaf;
+    lc += a - (carry_leaf ? 1u : 0u);
+    ih += b - (carry_int ? 1u : 0u);
+    it += pairs;
+    wave_sync();
   }
 }
 
@@ -178,7 +288,12 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     for (uint32_t i = tid; i < m; i += NT) {
       const uint64_t k = t.key[i];
       uint32_t r = 0;
-      for (uint32_t j = 0; j < m; ++j) r += t.key[j] < k;
+      uint32_t j = 0;
+      for (; j + 4 <= m; j += 4) {
+        const uint64_t k0 = t.key[j], k1 = t.key[j + 1], k2 = t.key[j + 2], k3 = t.key[j + 3];
+        r += (k0 < k) + (k1 < k) + (k2 < k) + (k3 < k);
+      }
+      for (; j < m; ++j) r += t.key[j] < k;
       t.mw[r] = k;
     }
     __syncthreads();
@@ -205,6 +320,11 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   __syncthreads();
 
   // ---- 3. GenerateCL rounds ------------------------------------------------
+  if constexpr (sizeof(IdT) == 2) {
+    // tree in LDS: one wave runs the rounds
+    if (wave == 0) rounds_one_wave(t, m, status);
+    __syncthreads();
+  } else {
   // every lane tracks the queues: leaves [lc, m), internal nodes [ih, it)
   uint32_t lc = 0, ih = 0, it = 0;
   for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
@@ -270,6 +390,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     it += pairs;
     __syncthreads();
   }
+  }
 
   // ---- 4. depths by pointer jumping ----------------------------------------
   const uint32_t nint = m - 1, root = m - 2;
@@ -323,11 +444,13 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   }
   bits = wave_sum_u64(bits);
   my_max = wave_max_u32(my_max);
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) my_min = min(my_min, (uint32_t)__shfl_xor(my_min, d, kWave));
   if (lane == 0) {
     atomicAdd((unsigned long long*)&sh.total, (unsigned long long)bits);
     atomicMax(&sh.lmax, my_max);
+    atomicMin(&sh.lmin, my_min);
   }
-  if (my_min != 0xFFFFFFFFu) atomicMin(&sh.lmin, my_min);
   __syncthreads();
 
   // ---- 5b. First and Entry (wave 0; lane j holds length j + 1) ----------------
@@ -369,7 +492,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     uint64_t pending = __ballot(valid);
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lv = __shfl(l, leader, kWave);
+      const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
       const uint64_t mask = __ballot(valid && l == lv);
       if (lane == lv - 1) creg += (uint32_t)__popcll(mask);
       pending &= ~mask;
@@ -394,9 +517,9 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     uint64_t pending = __ballot(valid);
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lv = __shfl(l, leader, kWave);
+      const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
       const uint64_t mask = __ballot(valid && l == lv);
-      const uint32_t slot0 = __shfl(breg, (int)lv - 1, kWave);
+      const uint32_t slot0 = (uint32_t)__builtin_amdgcn_readlane((int)breg, (int)lv - 1);
       if (valid && l == lv) {
         const uint32_t pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
         const uint32_t s = (uint32_t)t.usym[u];
@@ -409,20 +532,21 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   }
 }
 
-}  // namespace
+struct CbLds {
+  Shared sh;
+  uint64_t key[kCbLdsMaxUsed];
+  uint64_t iw[kCbLdsMaxUsed];
+  uint64_t mw[kCbLdsMaxUsed];  // also holds the depth arrays after the rounds
+  uint16_t mid[kCbLdsMaxUsed];
+  uint16_t par[2 * kCbLdsMaxUsed];
+  uint16_t usym[kCbLdsMaxUsed];
+  uint8_t clu[kCbLdsMaxUsed];
+};
 
+// The whole book from hist[A] by one workgroup of NT lanes.
 template <int NT>
-__global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict__ hist, hf_codebook book,
-                                                      char* ws, uint32_t* status) {
-  __shared__ Shared sh;
-  __shared__ uint64_t s_key[kCbLdsMaxUsed];
-  __shared__ uint64_t s_iw[kCbLdsMaxUsed];
-  __shared__ uint64_t s_mw[kCbLdsMaxUsed];  // also holds the depth arrays after the rounds
-  __shared__ uint16_t s_mid[kCbLdsMaxUsed];
-  __shared__ uint16_t s_par[2 * kCbLdsMaxUsed];
-  __shared__ uint16_t s_usym[kCbLdsMaxUsed];
-  __shared__ uint8_t s_clu[kCbLdsMaxUsed];
-
+__device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist, const hf_codebook& book,
+                                               char* ws, uint32_t* status, CbLds& L) {
   const uint32_t A = book.alphabet;
   const uint32_t tid = threadIdx.x;
   const uint32_t per = (A + NT - 1) / NT;
@@ -430,38 +554,118 @@ __global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict
   uint32_t c = 0;
   for (uint32_t s = s_lo; s < s_hi; ++s) c += (hist[s] != 0);
   uint32_t m;
-  const uint32_t base = block_exclusive_scan<NT / kWave>(c, sh.wtot, &m);
+  const uint32_t base = block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);
 
   if (m <= kCbLdsMaxUsed) {
     Tree<uint16_t> t;
-    t.key = s_key;
-    t.iw = s_iw;
-    t.mw = s_mw;
-    t.mid = s_mid;
-    t.par = s_par;
-    t.usym = s_usym;
-    t.clu = s_clu;
-    t.dA = (uint16_t*)s_mw;
+    t.key = L.key;
+    t.iw = L.iw;
+    t.mw = L.mw;
+    t.mid = L.mid;
+    t.par = L.par;
+    t.usym = L.usym;
+    t.clu = L.clu;
+    t.dA = (uint16_t*)L.mw;
     t.dB = t.dA + kCbLdsMaxUsed;
     t.nA = t.dB + kCbLdsMaxUsed;
     t.nB = t.nA + kCbLdsMaxUsed;
-    build_book<uint16_t, NT>(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+    build_book<uint16_t, NT>(t, L.sh, hist, A, s_lo, s_hi, base, m, book, status);
   } else {
-    const GlobalLayout L = global_layout(A);
+    const GlobalLayout G = global_layout(A);
     Tree<uint32_t> t;
-    t.key = (uint64_t*)(ws + L.key);
-    t.iw = (uint64_t*)(ws + L.iw);
-    t.mw = (uint64_t*)(ws + L.mw);
-    t.mid = (uint32_t*)(ws + L.mid);
-    t.par = (uint32_t*)(ws + L.par);
-    t.usym = (uint32_t*)(ws + L.usym);
-    t.clu = (uint8_t*)(ws + L.clu);
-    t.dA = (uint16_t*)(ws + L.dA);
-    t.dB = (uint16_t*)(ws + L.dB);
-    t.nA = (uint32_t*)(ws + L.nA);
-    t.nB = (uint32_t*)(ws + L.nB);
-    build_book<uint32_t, NT>(t, sh, hist, A, s_lo, s_hi, base, m, book, status);
+    t.key = (uint64_t*)(ws + G.key);
+    t.iw = (uint64_t*)(ws + G.iw);
+    t.mw = (uint64_t*)(ws + G.mw);
+    t.mid = (uint32_t*)(ws + G.mid);
+    t.par = (uint32_t*)(ws + G.par);
+    t.usym = (uint32_t*)(ws + G.usym);
+    t.clu = (uint8_t*)(ws + G.clu);
+    t.dA = (uint16_t*)(ws + G.dA);
+    t.dB = (uint16_t*)(ws + G.dB);
+    t.nA = (uint32_t*)(ws + G.nA);
+    t.nB = (uint32_t*)(ws + G.nB);
+    build_book<uint32_t, NT>(t, L.sh, hist, A, s_lo, s_hi, base, m, book, status);
   }
+}
+
+}  // namespace
+
+template <int NT>
+__global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict__ hist, hf_codebook book,
+                                                      char* ws, uint32_t* status) {
+  __shared__ CbLds lds;
+  codebook_block<NT>(hist, book, ws, status, lds);
+}
+
+// Batched stage 2: workgroup s sums stream s's per-slab counts into its
+// histogram, builds its book, then turns each slab's counts into the slab's
+// bit total (sum count * cl), its first bit (exclusive scan over the slabs)
+// and its last 32 content bits.
+constexpr int kBatchCbThreads = 256;
+
+__global__ __launch_bounds__(kBatchCbThreads) void batch_codebook_kernel(const BatchStream* __restrict__ streams) {
+  __shared__ CbLds lds;
+  __shared__ uint64_t s_bits[kBatchCbThreads / kWave];
+  const BatchStream bs = streams[blockIdx.x];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr uint32_t NW = kBatchCbThreads / kWave;
+  const uint32_t A = bs.A;
+  if (bs.n == 0 && tid == 0) bs.offsets[0] = 0;
+  for (uint32_t b = tid; b < A; b += kBatchCbThreads) {
+    uint32_t c = 0;
+    for (uint32_t g = 0; g < bs.nslabs; ++g) c += bs.part[(uint64_t)g * A + b];
+    bs.hist[b] = c;
+  }
+  __threadfence_block();
+  __syncthreads();
+  codebook_block<kBatchCbThreads>(bs.hist, bs.book, bs.cb_ws, bs.status, lds);
+  __threadfence_block();
+  __syncthreads();
+  // per-slab bit totals (wave w handles slabs w, w + NW, ...) and last 32 bits
+  for (uint32_t g = wave; g < bs.nslabs; g += NW) {
+    const uint32_t* row = bs.part + (uint64_t)g * A;
+    uint64_t bits = 0;
+    for (uint32_t b = lane; b < A; b += kWave) bits += (uint64_t)row[b] * bs.book.cl[b];
+    bits = wave_sum_u64(bits);
+    const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
+    const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
+    const uint32_t tail = bs.sym_bytes == 1 ? range_tail<1>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw)
+                                            : range_tail<2>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw);
+    if (lane == 0) {
+      bs.slab_G[g] = bits;  // turned into the exclusive prefix below
+      bs.slab_tail[g] = tail;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // exclusive scan of the slab totals, 256 slabs at a time
+  uint64_t carry = 0;
+  for (uint32_t g0 = 0; g0 < bs.nslabs; g0 += kBatchCbThreads) {
+    const uint32_t g = g0 + tid;
+    const uint64_t v = g < bs.nslabs ? bs.slab_G[g] : 0;
+    uint64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint64_t o = __shfl_up(inc, d, kWave);
+      if ((int)lane >= d) inc += o;
+    }
+    if (lane == kWave - 1) s_bits[wave] = inc;
+    __syncthreads();
+    uint64_t pre = carry, tot = 0;
+    for (uint32_t w = 0; w < NW; ++w) {
+      pre += w < wave ? s_bits[w] : 0;
+      tot += s_bits[w];
+    }
+    if (g < bs.nslabs) bs.slab_G[g] = pre + inc - v;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch_codebook(const BatchStream* d_streams, uint32_t nstreams, hipStream_t stream) {
+  batch_codebook_kernel<<<nstreams, kBatchCbThreads, 0, stream>>>(d_streams);
+  return hipGetLastError();
 }
 
 size_t codebook_workspace_bytes(uint32_t alphabet) {

@@ -77,4 +77,32 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
   return pre + inc - v;
 }
 
+template <int SB>
+__device__ __forceinline__ uint32_t sym_at(const void* p, uint64_t i) {
+  return SB == 1 ? (uint32_t)((const uint8_t*)p)[i] : (uint32_t)((const uint16_t*)p)[i];
+}
+
+// Last 32 content bits of the symbols [s_lo, s_hi) (right aligned, fewer if
+// the content is shorter), computed by wave 0: lane j codes symbol s_hi-1-j.
+template <int SB>
+__device__ __forceinline__ uint32_t range_tail(const void* sym, uint64_t s_lo, uint64_t s_hi, uint32_t A,
+                                               const uint8_t* cl, const uint64_t* cw) {
+  const uint32_t lane = lane_id();
+  uint32_t l = 0;
+  uint64_t c = 0;
+  if (lane < 32 && s_hi - s_lo > lane) {
+    const uint32_t s = sym_at<SB>(sym, s_hi - 1 - lane);
+    if (s < A) {
+      l = cl[s];
+      c = cw[s];
+    }
+  }
+  // bits already taken by lanes nearer the end
+  const uint32_t off = wave_inclusive_scan(l) - l;
+  uint32_t part = (off < 32) ? (uint32_t)(c << off) : 0u;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) part |= (uint32_t)__shfl_xor(part, d, kWave);
+  return part;
+}
+
 }  // namespace hf

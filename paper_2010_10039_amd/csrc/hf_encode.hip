@@ -88,11 +88,6 @@ struct EncArgs {
   uint32_t vec_ok;
 };
 
-template <int SB>
-__device__ __forceinline__ uint32_t sym_at(const void* p, uint64_t i) {
-  return SB == 1 ? (uint32_t)((const uint8_t*)p)[i] : (uint32_t)((const uint16_t*)p)[i];
-}
-
 template <int NS, int SB>
 struct Raw {
   static constexpr int kBytes = NS * SB;
@@ -160,29 +155,6 @@ __device__ __forceinline__ uint32_t tail_part(uint64_t c, uint32_t l, uint32_t p
   const uint32_t w = hi - lo;
   const uint64_t seg = (c >> (p + l - hi)) & ((w >= 64) ? ~0ull : ((1ull << w) - 1));
   return (uint32_t)(seg << (B - hi));
-}
-
-// Last 32 content bits of the symbols [s_lo, s_hi) (right aligned, fewer if
-// the content is shorter), computed by wave 0: lane j codes symbol s_hi-1-j.
-template <int SB>
-__device__ __forceinline__ uint32_t range_tail(const void* sym, uint64_t s_lo, uint64_t s_hi, uint32_t A,
-                                               const uint8_t* cl, const uint64_t* cw) {
-  const uint32_t lane = lane_id();
-  uint32_t l = 0;
-  uint64_t c = 0;
-  if (lane < 32 && s_hi - s_lo > lane) {
-    const uint32_t s = sym_at<SB>(sym, s_hi - 1 - lane);
-    if (s < A) {
-      l = cl[s];
-      c = cw[s];
-    }
-  }
-  // bits already taken by lanes nearer the end
-  const uint32_t off = wave_inclusive_scan(l) - l;
-  uint32_t part = (off < 32) ? (uint32_t)(c << off) : 0u;
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) part |= (uint32_t)__shfl_xor(part, d, kWave);
-  return part;
 }
 
 // ---------------------------------------------------------------------------
@@ -456,6 +428,69 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G);
 }
 
+// Batched stage 3: workgroup i encodes slab g of stream s for work item
+// items[i] = streams[s].item0 + g, whose first bit and predecessor tail the
+// batched codebook stage computed.  Each stream has its own alphabet,
+// symbol width and codebook.
+template <int R>
+__global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchStream* __restrict__ streams,
+                                                                   const uint32_t* __restrict__ item_stream,
+                                                                   const uint32_t* __restrict__ items) {
+  constexpr uint32_t T = kEncThreads << R;
+  extern __shared__ uint32_t lds[];
+  __shared__ EncShared sh;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t item = items[blockIdx.x];
+  const BatchStream& bs = streams[item_stream[item]];
+  const uint32_t g = item - bs.item0;
+  EncArgs a;
+  a.sym = bs.sym;
+  a.n = bs.n;
+  a.nblocks = bs.nblocks;
+  a.nslabs = bs.nslabs;
+  a.A = bs.A;
+  a.cl = bs.book.cl;
+  a.cw = bs.book.cw;
+  a.info = bs.book.info;
+  a.bits = nullptr;
+  a.tails = nullptr;
+  a.out = bs.out;
+  a.cap_words = bs.cap_words;
+  a.offsets = bs.offsets;
+  a.chunk_log2 = bs.chunk_log2;
+  a.nchunks = bs.nchunks;
+  a.status = bs.status;
+  a.vec_ok = ((uintptr_t)bs.sym % 16) == 0 ? 1u : 0u;
+  const uint32_t lmax = (uint32_t)a.info[1];
+  const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
+  const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
+  uint32_t* buf = lds;
+  uint32_t* tab = lds + T + 2;
+  uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
+  if (mode == kModeTable)
+    for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
+      const uint32_t l = s < a.A ? a.cl[s] : 0u;
+      tab[s] = l ? (((uint32_t)a.cw[s]) << 5) | l : 0u;
+    }
+  if (mode != kModeWide)
+    for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
+  if (tid == 0) {
+    sh.tail[0] = g > 0 ? bs.slab_tail[g - 1] : 0u;
+    sh.tailw = 0;
+  }
+  const uint64_t G = bs.slab_G[g];
+  __syncthreads();
+  if (bs.sym_bytes == 1) {
+    if (mode == kModeTable) encode_slab<R, 1, kModeTable>(a, tab, buf, dummy, sh, g, G);
+    else if (mode == kModeGlobal) encode_slab<R, 1, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
+    else encode_slab<R, 1, kModeWide>(a, tab, buf, dummy, sh, g, G);
+  } else {
+    if (mode == kModeTable) encode_slab<R, 2, kModeTable>(a, tab, buf, dummy, sh, g, G);
+    else if (mode == kModeGlobal) encode_slab<R, 2, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
+    else encode_slab<R, 2, kModeWide>(a, tab, buf, dummy, sh, g, G);
+  }
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 using EncodeFn = void (*)(EncArgs);
@@ -574,6 +609,24 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
   e = hipGetLastError();
   timer.after(stream);
   return e;
+}
+
+hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,
+                               const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
+                               hipStream_t stream) {
+  if (nitems == 0) return hipSuccess;
+  const size_t T = (size_t)kEncThreads << r;
+  const size_t lds = 4 * (T + 2 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
+  using Fn = void (*)(const BatchStream*, const uint32_t*, const uint32_t*);
+  Fn fn;
+  switch (r) {
+    case 3: fn = batch_encode_kernel<3>; break;
+    case 5: fn = batch_encode_kernel<5>; break;
+    default: fn = batch_encode_kernel<4>; break;
+  }
+  if (lds > (64u << 10)) (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(fn, dim3(nitems), dim3(kEncThreads), lds, stream, d_streams, d_item_stream, d_items);
+  return hipGetLastError();
 }
 
 }  // namespace hf

@@ -162,6 +162,49 @@ __global__ __launch_bounds__(kHistThreads) void hist_reduce_kernel(const uint32_
   }
 }
 
+// Batched stage 1: workgroup i counts slab g of stream s for work item
+// i = streams[s].item0 + g and stores the slab's counts.  The LDS holds
+// lds_words words: as many interleaved replicas of the alphabet as fit.
+__global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const BatchStream* __restrict__ streams,
+                                                                       const uint32_t* __restrict__ item_stream,
+                                                                       uint32_t lds_words) {
+  extern __shared__ uint32_t sub[];
+  const uint32_t item = blockIdx.x;
+  const uint32_t s = item_stream[item];
+  const BatchStream& bs = streams[s];
+  const uint32_t g = item - bs.item0;
+  const uint32_t A = bs.A;
+  uint32_t R = 1;
+  while (R < 16 && A * R * 2 <= lds_words) R *= 2;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < A * R; i += blockDim.x) sub[i] = 0;
+  __syncthreads();
+  const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
+  const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
+  bool bad = false;
+  if (bs.sym_bytes == 1) hist_range<1>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
+  else hist_range<2>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
+  __syncthreads();
+  uint32_t* row = bs.part + (uint64_t)g * A;
+  for (uint32_t b = tid; b < A; b += blockDim.x) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+    row[b] = c;
+  }
+  if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
+}
+
+hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
+                                  uint32_t max_alphabet, hipStream_t stream) {
+  if (nitems == 0) return hipSuccess;
+  const uint32_t lds_words = std::max<uint32_t>(4096u, max_alphabet);
+  const size_t lds = (size_t)lds_words * 4;
+  if (lds > (64u << 10))
+    (void)hipFuncSetAttribute((const void*)batch_histogram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  batch_histogram_kernel<<<nitems, kHistThreads, lds, stream>>>(d_streams, d_item_stream, lds_words);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream) {
   if (count == 0) return hipSuccess;
   uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (count + 255) / 256);

@@ -41,6 +41,10 @@ struct KernelTimer {
   }
 };
 
+// Takes the one-shot timer armed by hf_time_next_main_kernel on this host
+// thread (empty if none).
+KernelTimer take_main_timer();
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t stream);
 
@@ -70,6 +74,39 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
                          uint32_t chunk_log2, uint32_t r, uint32_t nslabs, const uint32_t* slab_hist,
                          uint32_t* out, uint64_t cap_words, uint64_t* offsets, void* ws,
                          uint32_t* status, hipStream_t stream, const KernelTimer& timer);
+
+// One stream of a batched encode, as the batch kernels see it.  Slabs of a
+// stream follow the same block partition as the single-stream path.
+struct BatchStream {
+  const void* sym;
+  uint64_t n;
+  uint64_t nblocks;
+  uint32_t sym_bytes;
+  uint32_t A;
+  uint32_t nslabs;
+  uint32_t item0;       // first (stream, slab) work item of this stream
+  uint32_t r;           // reduce_log2 used for this stream
+  uint32_t chunk_log2;
+  uint64_t nchunks;
+  uint32_t* part;       // [nslabs * A] per-slab counts
+  uint32_t* hist;       // [A]
+  hf_codebook book;
+  char* cb_ws;          // codebook tree when more than kCbLdsMaxUsed symbols are used
+  uint64_t* slab_G;     // [nslabs] first bit of each slab
+  uint32_t* slab_tail;  // [nslabs] last 32 content bits of each slab
+  uint32_t* out;
+  uint64_t cap_words;
+  uint64_t* offsets;
+  uint32_t* status;
+};
+
+hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
+                                  uint32_t max_alphabet, hipStream_t stream);
+hipError_t launch_batch_codebook(const BatchStream* d_streams, uint32_t nstreams, hipStream_t stream);
+// r in {3, 4, 5} (others run as 4).
+hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,
+                               const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
+                               hipStream_t stream);
 
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
                                uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,

@@ -292,3 +292,82 @@ class Encoder:
         hf_encode(sym, self.book, self.chunk, self.r, self.out, self.offsets, self.ws, self.status,
                   self.nslabs, self.slab_hist)
         return self.out, self.offsets
+
+
+class hf_stream_desc(ctypes.Structure):
+    _fields_ = [
+        ("sym", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("sym_bytes", ctypes.c_uint32),
+        ("chunk_symbols", ctypes.c_uint32),
+        ("reduce_log2", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("hist", ctypes.c_void_p),
+        ("book", hf_codebook),
+        ("out", ctypes.c_void_p),
+        ("out_capacity_words", ctypes.c_uint64),
+        ("chunk_bit_offsets", ctypes.c_void_p),
+    ]
+
+
+_lib.hf_batch_workspace_bytes.argtypes = [ctypes.POINTER(hf_stream_desc), _U32]
+_lib.hf_batch_workspace_bytes.restype = _SZ
+_lib.hf_encode_batch.argtypes = [ctypes.POINTER(hf_stream_desc), _U32, _P, _SZ, _P, _P]
+_lib.hf_encode_batch.restype = ctypes.c_int
+
+
+def hf_batch_workspace_bytes(descs) -> int:
+    return int(_lib.hf_batch_workspace_bytes(descs, len(descs)))
+
+
+def hf_encode_batch(descs, ws: torch.Tensor, status: torch.Tensor) -> None:
+    """Encode every stream of the ctypes hf_stream_desc array `descs`."""
+    _check(_lib.hf_encode_batch(descs, len(descs), _ptr(ws), ws.numel(), _ptr(status), _stream()),
+           "hf_encode_batch")
+
+
+class BatchEncoder:
+    """Buffers for one batch of independent streams encoded by a single
+    hf_encode_batch call: per stream a codebook, a histogram, output words
+    and chunk offsets; one workspace and one status word per stream."""
+
+    def __init__(self, syms, alphabets, chunk_symbols=4096, reduce_log2=0, device="cuda"):
+        self.syms = list(syms)
+        n = len(self.syms)
+        self.alphabets = list(alphabets)
+        chunks = chunk_symbols if isinstance(chunk_symbols, (list, tuple)) else [chunk_symbols] * n
+        rs = reduce_log2 if isinstance(reduce_log2, (list, tuple)) else [reduce_log2] * n
+        self.chunks = list(chunks)
+        self.books, self.hists, self.outs, self.offsets = [], [], [], []
+        self.descs = (hf_stream_desc * n)()
+        for i, (x, A) in enumerate(zip(self.syms, self.alphabets)):
+            sb = _sym_bytes(x)
+            book = Codebook.empty(A, device)
+            hist = torch.empty(A, dtype=torch.int32, device=device)
+            out = torch.empty(max(1, hf_bound_words(x.numel(), A)), dtype=torch.int32, device=device)
+            offs = torch.empty((x.numel() + chunks[i] - 1) // chunks[i] + 1, dtype=torch.int64, device=device)
+            self.books.append(book)
+            self.hists.append(hist)
+            self.outs.append(out)
+            self.offsets.append(offs)
+            d = self.descs[i]
+            d.sym = x.data_ptr() if x.numel() else 0
+            d.n = x.numel()
+            d.sym_bytes = sb
+            d.chunk_symbols = chunks[i]
+            d.reduce_log2 = rs[i]
+            d.reserved = 0
+            d.hist = hist.data_ptr()
+            d.book = book.struct()
+            d.out = out.data_ptr()
+            d.out_capacity_words = out.numel()
+            d.chunk_bit_offsets = offs.data_ptr()
+        nbytes = hf_batch_workspace_bytes(self.descs)
+        if nbytes == 0:
+            raise HFError(HF_ERR_ARG, "BatchEncoder")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(n, dtype=torch.int32, device=device)
+
+    def run(self):
+        hf_encode_batch(self.descs, self.ws, self.status)
+        return self.outs, self.offsets

@@ -121,6 +121,101 @@ def skewed_histogram(alphabet: int, total: int, seed: int = 0, kind: str = "norm
     return np.bincount(v.astype(np.int64), minlength=alphabet).astype(np.uint32)
 
 
+def batched_streams(nstreams: int = 512, seed: int = 1000, min_log2: float = 16.0, max_log2: float = 26.0,
+                    alphabets=(256, 1024, 4096, 8192), sigma_range=(0.5, 50.0), device: str = "cpu"):
+    """Independent streams of uneven size, each with its own alphabet and
+    distribution (the batched workload).
+
+    Stream i (seed + i): n = floor(exp(U(ln 2^min_log2, ln 2^max_log2)));
+    uint8 with alphabet 256 with probability 1/2, else uint16 with an
+    alphabet drawn from `alphabets`; values clip(rint(N(A/2, sigma)), 0, A-1)
+    with sigma log-uniform in sigma_range.  Sizes and parameters come from
+    numpy; the values are drawn by torch on `device` with a seeded generator.
+    Returns (list of tensors, list of alphabets)."""
+    import torch
+
+    syms, alph = [], []
+    for i in range(nstreams):
+        rng = np.random.default_rng(seed + i)
+        n = int(math.exp(rng.uniform(min_log2 * math.log(2), max_log2 * math.log(2))))
+        if rng.random() < 0.5:
+            A, dt = 256, torch.uint8
+        else:
+            A, dt = int(rng.choice([a for a in alphabets if a > 256] or [256])), torch.int16
+        sigma = math.exp(rng.uniform(math.log(sigma_range[0]), math.log(sigma_range[1])))
+        g = torch.Generator(device=device).manual_seed(seed * 7919 + i)
+        v = torch.randn(n, generator=g, device=device, dtype=torch.float32) * sigma + A / 2
+        v = torch.clamp(torch.round(v), 0, A - 1)
+        syms.append(v.to(torch.int32).to(dt))
+        alph.append(A)
+    return syms, alph
+
+
+def skew_normal_codes(n: int, alphabet: int, sigma: float, shape: float, generator, device="cpu"):
+    """clip(rint(A/2 + sigma * y), 0, A-1) with y skew-normal of shape
+    `shape`: y = d |z0| + sqrt(1 - d^2) z1, d = shape / sqrt(1 + shape^2),
+    z0, z1 i.i.d. N(0, 1).  Returns int32 values."""
+    import torch
+
+    d = shape / math.sqrt(1.0 + shape * shape)
+    z0 = torch.randn(n, generator=generator, device=device)
+    y = torch.randn(n, generator=generator, device=device).mul_(math.sqrt(1.0 - d * d))
+    y.add_(z0.abs_(), alpha=d)
+    del z0
+    return torch.clamp(torch.round(y.mul_(sigma).add_(alphabet / 2)), 0, alphabet - 1).to(torch.int32)
+
+
+def zipf_codes(n: int, alphabet: int, s: float, generator, device="cpu"):
+    """Zipf(s) over a random permutation of [0, A): rank k (1-based) has
+    probability proportional to k^-s; sampled by inverting the CDF.
+    Returns int32 values."""
+    import torch
+
+    k = torch.arange(1, alphabet + 1, dtype=torch.float64, device=device)
+    cdf = torch.cumsum(k.pow(-s), 0)
+    cdf = (cdf / cdf[-1]).to(torch.float32)
+    perm = torch.randperm(alphabet, generator=generator, device=device).to(torch.int32)
+    u = torch.rand(n, generator=generator, device=device)
+    idx = torch.clamp(torch.searchsorted(cdf, u), max=alphabet - 1)
+    return perm[idx]
+
+
+def served_requests(nreq: int = 200, seed: int = 2000, qps: float = 2000.0, min_bytes: float = 2.0 ** 20,
+                    max_bytes: float = 2.0 ** 29, device: str = "cpu"):
+    """A trace of compression requests (the served workload).
+
+    Request i (seed + i): arrival = sum of i+1 exponential gaps of mean
+    1/qps seconds; size log-uniform in [min_bytes, max_bytes]; uint8 with
+    alphabet 256, or uint16 with alphabet 2^k, k uniform in 10..16; half the
+    requests skew-normal (shape uniform in [-8, 8], sigma log-uniform in
+    [0.5, A/8]), half Zipf (s uniform in [1.05, 1.6]).  The values are drawn
+    by torch on `device`.  Returns a list of (arrival_s, symbols, alphabet,
+    kind)."""
+    import torch
+
+    out = []
+    t = 0.0
+    for i in range(nreq):
+        rng = np.random.default_rng(seed + i)
+        t += rng.exponential(1.0 / qps)
+        nbytes = math.exp(rng.uniform(math.log(min_bytes), math.log(max_bytes)))
+        if rng.random() < 0.5:
+            sb, A, dt = 1, 256, torch.uint8
+        else:
+            sb, A, dt = 2, 1 << int(rng.integers(10, 17)), torch.int16
+        n = max(1, int(nbytes) // sb)
+        g = torch.Generator(device=device).manual_seed(seed * 7919 + i)
+        if rng.random() < 0.5:
+            sigma = math.exp(rng.uniform(math.log(0.5), math.log(A / 8)))
+            v = skew_normal_codes(n, A, sigma, float(rng.uniform(-8, 8)), g, device)
+            kind = "skew-normal"
+        else:
+            v = zipf_codes(n, A, float(rng.uniform(1.05, 1.6)), g, device)
+            kind = "zipf"
+        out.append((t, v.to(dt), A, kind))
+    return out
+
+
 WORKLOADS = {
     "gaussian_1M_u16_A1024": dict(kind="gaussian", n=1 << 20, alphabet=1024, chunk=4096),
     "lorenzo3d_512cube_u16_A1024": dict(kind="lorenzo", dim=512, alphabet=1024, chunk=4096),

@@ -96,3 +96,41 @@ def test_slab_count_bounds(lib):
     assert lib.hf_slab_count(1 << 20, 65536) == 0  # no per-slab counts for large alphabets
     assert 1 <= lib.hf_slab_count(5000, 1024) <= 2  # at most one slab per 4096-symbol block
     assert 1 <= lib.hf_slab_count(1 << 27, 1024) <= (1 << 27) // 4096
+
+
+def test_batch_descriptor_checks(lib):
+    """hf_batch_workspace_bytes is 0 for an invalid descriptor, and
+    hf_encode_batch rejects it before launching anything."""
+    from paper_2010_10039_amd import hf
+
+    def desc(**kw):
+        d = hf.hf_stream_desc()
+        d.sym, d.n, d.sym_bytes, d.chunk_symbols = 0x1000, 1000, 2, 4096
+        d.hist, d.out, d.out_capacity_words, d.chunk_bit_offsets = 0, 0x2000, 1000, 0x3000
+        b = hf.hf_codebook()
+        b.alphabet = 1024
+        b.cl = b.cw = b.first = b.entry = b.rev = b.info = 0x4000
+        d.book = b
+        for k, v in kw.items():
+            if k == "alphabet":
+                d.book.alphabet = v
+            else:
+                setattr(d, k, v)
+        return d
+
+    f = lib.hf_batch_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.POINTER(hf.hf_stream_desc), ctypes.c_uint32]
+    ok = (hf.hf_stream_desc * 2)(desc(), desc(n=5_000_000, sym_bytes=1, alphabet=256, reduce_log2=3))
+    assert f(ok, 2) >= 256
+    bad = [dict(alphabet=8193), dict(sym_bytes=1, alphabet=300), dict(chunk_symbols=1000),
+           dict(chunk_symbols=128), dict(reduce_log2=2), dict(reduce_log2=6), dict(reserved=1),
+           dict(n=1 << 32), dict(sym=0x1001), dict(chunk_bit_offsets=0)]
+    g = lib.hf_encode_batch
+    g.restype = ctypes.c_int
+    g.argtypes = [ctypes.POINTER(hf.hf_stream_desc), ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    for kw in bad:
+        arr = (hf.hf_stream_desc * 2)(desc(), desc(**kw))
+        assert f(arr, 2) == 0, kw
+        assert g(arr, 2, ctypes.c_void_p(0x10000), 1 << 20, ctypes.c_void_p(0x20000), None) == 1, kw
