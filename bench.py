@@ -52,6 +52,35 @@ def parse():
     return p.parse_args()
 
 
+KERNEL_SOURCES = ["paper_2010_10039_amd/csrc/hf_encode.hip", "paper_2010_10039_amd/csrc/hf_device.h",
+                  "paper_2010_10039_amd/csrc/hf_kernels.h"]
+
+
+def measured_traffic(kernel: str, profile: str):
+    """HBM bytes per dispatch of `kernel` from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a device copy), or
+    None when the summary is missing or the kernel's sources changed since
+    the counters were taken (sha256 over KERNEL_SOURCES)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "traffic" and parts[1] == kernel:
+            kv = dict(p.split("=", 1) for p in parts[2:])
+            if kv.get("sources") != h.hexdigest():
+                return None
+            return {"fetch_bytes": int(kv["fetch"]), "write_bytes": int(kv["write"]),
+                    "bytes": int(kv["fetch"]) + int(kv["write"]), "source": f"profiles/{profile}"}
+    return None
+
+
 def cpu_baseline(x: np.ndarray, A: int, chunk: int, budget_s: float):
     """The oracle (serial C: histogram, heap codebook, serial bit packer) on
     the same input, repeated over whole passes until ~budget_s has elapsed."""
@@ -429,6 +458,11 @@ def main():
         "bytes_per_launch": enc_bytes,
         "avg_launch_us": round(stage_ms["encode"] * 1e3, 2),
     }
+    if args.workload == "lorenzo3d_512cube_u16_A1024" and args.chunk == 4096 and r_eff == 4:
+        t = measured_traffic("encode_kernel", "encode_kernel_lorenzo512_hbm_traffic.txt")
+        if t is not None:
+            roofline["traffic"] = t["bytes"]
+            roofline["traffic_detail"] = t
     cpu = None
     if args.cpu_seconds > 0:
         log("timing the CPU oracle")

@@ -129,7 +129,7 @@ class Autotuner:
             self.table[f"{w}/{a}/bany"] = {"r": r, "chunk": c, "score": round(score[kbest], 3)}
 
 
-def tune(widths_alphabets=((1, 256), (2, 1024), (2, 4096), (2, 8192)), n: int = 1 << 22,
+def tune(widths_alphabets=((1, 256), (2, 1024), (2, 4096), (2, 8192)), n: int = 1 << 25,
          reps: int = 5, seed: int = 4242, device: str = "cuda") -> Autotuner:
     """Times hf_encode over R_CHOICES x CHUNK_CHOICES for every bucket on a
     seeded discrete Gaussian stream whose sigma puts beta in that bucket's
@@ -183,7 +183,7 @@ def main() -> None:
 
     p = argparse.ArgumentParser(description="time the encoder per bucket and write the table")
     p.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json"))
-    p.add_argument("--n", type=int, default=1 << 22)
+    p.add_argument("--n", type=int, default=1 << 25)
     args = p.parse_args()
     t0 = time.perf_counter()
     tuner = tune(n=args.n)

@@ -2,6 +2,7 @@
 // planning and the three stage launches (histogram of every slab of every
 // stream; one codebook per stream plus slab offsets; encoding of every
 // slab), whatever the number of streams.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -37,16 +38,25 @@ uint32_t batch_slabs(uint64_t n, uint32_t sym_bytes, uint32_t alphabet) {
   return (uint32_t)(s > 0 ? s : 1);
 }
 
-uint32_t group_of(uint32_t r) { return r == 3 ? 0u : (r == 5 ? 2u : 1u); }
+// Launch groups: the histogram by alphabet class (LDS size), the encoder by
+// reduction factor and alphabet class (tile buffer and code table size).
+constexpr uint32_t kAlphaClasses[3] = {1024, 4096, 8192};
+constexpr uint32_t kRs[3] = {3, 4, 5};
+constexpr int kHistGroups = 2;     // alphabet <= 4096, <= 8192
+constexpr int kEncGroups = 3 * 3;  // r x alphabet class
+
+uint32_t alpha_class(uint32_t A) { return A <= kAlphaClasses[0] ? 0u : (A <= kAlphaClasses[1] ? 1u : 2u); }
+uint32_t r_index(uint32_t r) { return r == 3 ? 0u : (r == 5 ? 2u : 1u); }
 
 struct Plan {
   std::vector<hf::BatchStream> bs;
   std::vector<uint32_t> item_stream;  // stream of every item
-  std::vector<uint32_t> items;        // items grouped by r (3, 4, 5)
-  uint32_t group_count[3] = {0, 0, 0};
-  uint32_t group_start[3] = {0, 0, 0};
-  uint32_t max_alphabet = 1;
-  size_t off_streams = 0, off_item_stream = 0, off_items = 0, header_bytes = 0, total_bytes = 0;
+  std::vector<uint32_t> hist_items;   // items by histogram group
+  std::vector<uint32_t> enc_items;    // items by encoder group
+  uint32_t hist_start[kHistGroups] = {}, hist_count[kHistGroups] = {};
+  uint32_t enc_start[kEncGroups] = {}, enc_count[kEncGroups] = {};
+  size_t off_streams = 0, off_item_stream = 0, off_hist_items = 0, off_enc_items = 0, header_bytes = 0,
+         total_bytes = 0;
 };
 
 hf_status validate(const hf_stream_desc& d) {
@@ -63,7 +73,9 @@ hf_status validate(const hf_stream_desc& d) {
   return HF_OK;
 }
 
-// Lays out the workspace (ws may be null to only size it).
+// Lays out the workspace (ws may be null to only size it).  Within every
+// launch group, the slabs of streams with more symbols per slab come first,
+// so the longest work items start earliest.
 hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t* d_status, Plan& p) {
   size_t o = 0;
   p.off_streams = o;
@@ -77,13 +89,14 @@ hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t
   if (nitems >= (1ull << 31)) return HF_ERR_ARG;
   p.off_item_stream = o;
   o += align256(4 * nitems);
-  p.off_items = o;
+  p.off_hist_items = o;
+  o += align256(4 * nitems);
+  p.off_enc_items = o;
   o += align256(4 * nitems);
   p.header_bytes = o;
   p.bs.resize(ns);
   p.item_stream.clear();
   p.item_stream.reserve(nitems);
-  std::vector<uint32_t> groups[3];
   for (uint32_t s = 0; s < ns; ++s) {
     const hf_stream_desc& d = descs[s];
     hf::BatchStream& b = p.bs[s];
@@ -114,21 +127,49 @@ hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t
     const size_t cb = hf::codebook_workspace_bytes(A);
     b.cb_ws = cb ? ws + o : nullptr;
     o += align256(cb);
-    b.slab_G = (uint64_t*)(ws + o);
+    b.slab_bits = (uint64_t*)(ws + o);
     o += align256((size_t)b.nslabs * 8);
     b.slab_tail = (uint32_t*)(ws + o);
     o += align256((size_t)b.nslabs * 4);
-    if (A > p.max_alphabet) p.max_alphabet = A;
-    for (uint32_t g = 0; g < b.nslabs; ++g) {
-      groups[group_of(b.r)].push_back((uint32_t)p.item_stream.size());
-      p.item_stream.push_back(s);
-    }
+    for (uint32_t g = 0; g < b.nslabs; ++g) p.item_stream.push_back(s);
   }
-  p.items.clear();
-  for (int k = 0; k < 3; ++k) {
-    p.group_start[k] = (uint32_t)p.items.size();
-    p.group_count[k] = (uint32_t)groups[k].size();
-    p.items.insert(p.items.end(), groups[k].begin(), groups[k].end());
+  // streams by descending symbols per slab
+  std::vector<uint32_t> order(ns);
+  for (uint32_t s = 0; s < ns; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    const hf::BatchStream &a = p.bs[x], &b = p.bs[y];
+    const uint64_t pa = a.nslabs ? a.n / a.nslabs : 0, pb = b.nslabs ? b.n / b.nslabs : 0;
+    return pa > pb;
+  });
+  std::vector<uint32_t> hcount(kHistGroups, 0), ecount(kEncGroups, 0);
+  for (uint32_t s = 0; s < ns; ++s) {
+    const hf::BatchStream& b = p.bs[s];
+    hcount[b.A <= 4096 ? 0 : 1] += b.nslabs;
+    ecount[r_index(b.r) * 3 + alpha_class(b.A)] += b.nslabs;
+  }
+  uint32_t acc = 0;
+  for (int k = 0; k < kHistGroups; ++k) {
+    p.hist_start[k] = acc;
+    p.hist_count[k] = hcount[k];
+    acc += hcount[k];
+  }
+  acc = 0;
+  for (int k = 0; k < kEncGroups; ++k) {
+    p.enc_start[k] = acc;
+    p.enc_count[k] = ecount[k];
+    acc += ecount[k];
+  }
+  p.hist_items.assign(nitems, 0);
+  p.enc_items.assign(nitems, 0);
+  std::vector<uint32_t> hpos(p.hist_start, p.hist_start + kHistGroups), epos(p.enc_start, p.enc_start + kEncGroups);
+  for (uint32_t s : order) {
+    const hf::BatchStream& b = p.bs[s];
+    uint32_t& hp = hpos[b.A <= 4096 ? 0 : 1];
+    uint32_t& ep = epos[r_index(b.r) * 3 + alpha_class(b.A)];
+    for (uint32_t g = 0; g < b.nslabs; ++g) {
+      p.hist_items[hp++] = b.item0 + g;
+      p.enc_items[ep++] = b.item0 + g;
+    }
   }
   p.total_bytes = o;
   return HF_OK;
@@ -207,23 +248,30 @@ hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* 
     if (!sg) return HF_ERR_LAUNCH;
     memcpy(sg->host + p.off_streams, p.bs.data(), sizeof(hf::BatchStream) * nstreams);
     memcpy(sg->host + p.off_item_stream, p.item_stream.data(), 4 * p.item_stream.size());
-    memcpy(sg->host + p.off_items, p.items.data(), 4 * p.items.size());
+    memcpy(sg->host + p.off_hist_items, p.hist_items.data(), 4 * p.hist_items.size());
+    memcpy(sg->host + p.off_enc_items, p.enc_items.data(), 4 * p.enc_items.size());
     if (hipMemcpyAsync(ws, sg->host, p.header_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return HF_ERR_LAUNCH;
     if (hipEventRecord(sg->done, st) != hipSuccess) return HF_ERR_LAUNCH;
   }
   const hf::BatchStream* d_streams = (const hf::BatchStream*)(ws + p.off_streams);
   const uint32_t* d_item_stream = (const uint32_t*)(ws + p.off_item_stream);
-  const uint32_t* d_items = (const uint32_t*)(ws + p.off_items);
+  const uint32_t* d_hist_items = (const uint32_t*)(ws + p.off_hist_items);
+  const uint32_t* d_enc_items = (const uint32_t*)(ws + p.off_enc_items);
   const uint32_t nitems = (uint32_t)p.item_stream.size();
-  if (hf::launch_batch_histogram(d_streams, d_item_stream, nitems, p.max_alphabet, st) != hipSuccess)
-    return HF_ERR_LAUNCH;
+  const uint32_t hist_alpha[kHistGroups] = {4096, 8192};
+  for (int k = 0; k < kHistGroups; ++k) {
+    if (!p.hist_count[k]) continue;
+    if (hf::launch_batch_histogram(d_streams, d_item_stream, d_hist_items + p.hist_start[k], p.hist_count[k],
+                                   hf::batch_hist_lds_words(hist_alpha[k]), st) != hipSuccess)
+      return HF_ERR_LAUNCH;
+  }
   if (hf::launch_batch_codebook(d_streams, nstreams, st) != hipSuccess) return HF_ERR_LAUNCH;
+  if (hf::launch_batch_slab_bits(d_streams, d_item_stream, nitems, st) != hipSuccess) return HF_ERR_LAUNCH;
   timer.before(st);
-  const uint32_t rs[3] = {3, 4, 5};
-  for (int k = 0; k < 3; ++k) {
-    if (!p.group_count[k]) continue;
-    if (hf::launch_batch_encode(d_streams, d_item_stream, d_items + p.group_start[k], p.group_count[k], rs[k],
-                                p.max_alphabet, st) != hipSuccess)
+  for (int k = 0; k < kEncGroups; ++k) {
+    if (!p.enc_count[k]) continue;
+    if (hf::launch_batch_encode(d_streams, d_item_stream, d_enc_items + p.enc_start[k], p.enc_count[k],
+                                kRs[k / 3], kAlphaClasses[k % 3], st) != hipSuccess)
       return HF_ERR_LAUNCH;
   }
   timer.after(st);

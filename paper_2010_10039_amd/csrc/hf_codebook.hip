@@ -93,6 +93,7 @@ struct Tree {
 constexpr int kCbMaxWaves = 16;
 
 struct Shared {
+  uint64_t wsum[kCbMaxWaves];
   uint32_t wtot[kCbMaxWaves];
   uint32_t cnt[kMaxLen + 1];
   uint32_t cntw[kCbMaxWaves][kMaxLen + 1];
@@ -543,6 +544,287 @@ struct CbLds {
   uint8_t clu[kCbLdsMaxUsed];
 };
 
+// ---------------------------------------------------------------------------
+// Books of at most kSmallUsed used symbols whose counts sum below 2^32 - 1:
+// every weight fits 32 bits, the leaves fit four registers of one wave, and
+// one wave runs the rounds with both candidate runs held in registers.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSmallUsed = 256;
+constexpr uint32_t kInf32 = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t readlane32(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
+template <int NT>
+__device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __restrict__ hist, uint32_t s_lo,
+                                                 uint32_t s_hi, uint32_t base, uint32_t m,
+                                                 const hf_codebook& book, uint32_t* status) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t wave = tid / kWave;
+  uint64_t* key = L.key;                    // [m] (count << 16 | u), u = compact index
+  uint16_t* usym = L.usym;                  // [m] compact index -> symbol
+  uint32_t* lw = (uint32_t*)L.iw;           // [m] leaf weights, sorted by (count, u)
+  uint32_t* iw = lw + kSmallUsed;           // [m-1] internal weights, creation order
+  uint16_t* lu = L.mid;                     // [m] compact index of each sorted leaf
+  uint16_t* parl = L.par;                   // [m] parent of each sorted leaf
+  uint16_t* pari = L.par + kSmallUsed;      // [m-1] parent of each internal node
+  uint16_t* dep = L.par + 2 * kSmallUsed;   // [m-1] distance to the current jump target
+  uint16_t* nxt = L.par + 3 * kSmallUsed;   // [m-1] jump target
+
+  // ---- 1. compaction ---------------------------------------------------------
+  {
+    uint32_t u = base;
+    for (uint32_t s = s_lo; s < s_hi; ++s) {
+      const uint32_t h = hist[s];
+      if (h) {
+        key[u] = ((uint64_t)h << 16) | u;
+        usym[u] = (uint16_t)s;
+        ++u;
+      } else {
+        book.cl[s] = 0;
+        book.cw[s] = 0;
+      }
+    }
+  }
+  for (uint32_t i = tid; i < kSmallUsed; i += NT) iw[i] = 0;
+  for (uint32_t l = tid; l <= kMaxLen; l += NT) L.sh.cnt[l] = 0;
+  __syncthreads();
+
+  // ---- 2. rank sort: wave w ranks keys [64w, 64w + 64) against all keys -------
+  if (wave < kSmallUsed / kWave) {
+    const uint32_t e = wave * kWave + lane;
+    const uint64_t k = e < m ? key[e] : ~0ull;
+    uint64_t K[kSmallUsed / kWave];
+#pragma unroll
+    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r) K[r] = r * kWave + lane < m ? key[r * kWave + lane] : ~0ull;
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r) {
+      const uint32_t nl = m > r * kWave ? min((uint32_t)kWave, m - r * kWave) : 0u;
+#pragma unroll 4
+      for (uint32_t l = 0; l < nl; ++l) rank += readlane64(K[r], (int)l) < k;
+    }
+    if (e < m) {
+      lw[rank] = (uint32_t)(k >> 16);
+      lu[rank] = (uint16_t)(k & 0xFFFFu);
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+
+  // ---- 3. GenerateCL rounds, one wave -----------------------------------------
+  // Lane j holds leaf lc + j and internal node ih + j of this round's runs;
+  // the merge position of each comes from counting over the other run.
+  {
+    uint32_t lc = 0, ih = 0, it = 0;
+    for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
+      if (round >= m) {  // every round creates at least one node
+        if (lane == 0) raise_status(status, HF_ERR_INTERNAL);
+        break;
+      }
+      const uint32_t b = it - ih;
+      const uint32_t RL = lc + lane < m ? lw[lc + lane] : kInf32;
+      const uint32_t RI = lane < b ? iw[ih + lane] : kInf32;
+      const uint32_t l0 = readlane32(RL, 0), l1 = readlane32(RL, 1);
+      const uint32_t i0 = readlane32(RI, 0), i1 = readlane32(RI, 1);
+      uint32_t w1, w2;  // the two lightest nodes, leaf first on equal weight
+      if (l0 <= i0) {
+        w1 = l0;
+        w2 = l1 <= i0 ? l1 : i0;
+      } else {
+        w1 = i0;
+        w2 = l0 <= i1 ? l0 : i1;
+      }
+      const uint32_t tw = w1 + w2;  // <= the sum of all counts < 2^32 - 1
+      uint32_t a = (uint32_t)__popcll(__ballot(RL <= tw));
+      if (a == (uint32_t)kWave) {
+        for (uint32_t p = lc + kWave; p < m; p += kWave) {
+          const uint32_t v = p + lane < m ? lw[p + lane] : kInf32;
+          const uint32_t c = (uint32_t)__popcll(__ballot(v <= tw));
+          a += c;
+          if (c < (uint32_t)kWave) break;
+        }
+      }
+      const uint32_t total = a + b, pairs = total >> 1;
+      uint32_t last_leaf, last_int;
+      if (a <= (uint32_t)kWave && b <= (uint32_t)kWave) {
+        uint32_t cl_ = 0, ci = 0;
+        for (uint32_t q = 0; q < b; ++q) cl_ += readlane32(RI, q) < RL;   // internals lighter than my leaf
+        for (uint32_t j = 0; j < a; ++j) ci += readlane32(RL, j) <= RI;   // leaves no heavier than my node
+        const uint32_t pl = lane + cl_, pi = lane + ci;
+        if (lane < a && pl < 2 * pairs) {
+          parl[lc + lane] = (uint16_t)(it + (pl >> 1));
+          atomicAdd(&iw[it + (pl >> 1)], RL);
+        }
+        if (lane < b && pi < 2 * pairs) {
+          pari[ih + lane] = (uint16_t)(it + (pi >> 1));
+          atomicAdd(&iw[it + (pi >> 1)], RI);
+        }
+        last_leaf = a ? readlane32(RL, a - 1) : 0u;
+        last_int = b ? readlane32(RI, b - 1) : 0u;
+      } else {
+        for (uint32_t j = lane; j < a; j += kWave) {
+          const uint32_t w = lw[lc + j];
+          uint32_t lo = ih, hi = it;  // first internal node not lighter than w
+          while (lo < hi) {
+            const uint32_t md = (lo + hi) >> 1;
+            if (iw[md] < w) lo = md + 1;
+            else hi = md;
+          }
+          const uint32_t pos = j + (lo - ih);
+          if (pos < 2 * pairs) {
+            parl[lc + j] = (uint16_t)(it + (pos >> 1));
+            atomicAdd(&iw[it + (pos >> 1)], w);
+          }
+        }
+        for (uint32_t q = lane; q < b; q += kWave) {
+          const uint32_t w = iw[ih + q];
+          uint32_t lo = lc, hi = lc + a;  // first leaf heavier than w
+          while (lo < hi) {
+            const uint32_t md = (lo + hi) >> 1;
+            if (lw[md] <= w) lo = md + 1;
+            else hi = md;
+          }
+          const uint32_t pos = q + (lo - lc);
+          if (pos < 2 * pairs) {
+            pari[ih + q] = (uint16_t)(it + (pos >> 1));
+            atomicAdd(&iw[it + (pos >> 1)], w);
+          }
+        }
+        last_leaf = a ? readlane32(lw[lc + a - 1], 0) : 0u;
+        last_int = b ? readlane32(iw[it - 1], 0) : 0u;
+      }
+      // an odd node out is the heaviest of the merge (internal after leaf on a tie)
+      const bool carry_leaf = (total & 1) && a > 0 && (b == 0 || last_leaf > last_int);
+      const bool carry_int = (total & 1) && !carry_leaf;
+      lc += a - (carry_leaf ? 1u : 0u);
+      ih += b - (carry_int ? 1u : 0u);
+      it += pairs;
+      wave_sync();
+    }
+  }
+
+  // ---- 4. depths of internal nodes by pointer jumping ----------------------------
+  const uint32_t nint = m - 1, root = m - 2;
+  constexpr uint32_t NR = kSmallUsed / kWave;
+  uint32_t d[NR], nx[NR];
+#pragma unroll
+  for (uint32_t r = 0; r < NR; ++r) {
+    const uint32_t k = r * kWave + lane;
+    const bool valid = k < nint && k != root;
+    d[r] = valid ? 1u : 0u;
+    nx[r] = valid ? (uint32_t)pari[k] : root;
+  }
+  for (uint32_t step = 0;; ++step) {
+#pragma unroll
+    for (uint32_t r = 0; r < NR; ++r) {
+      const uint32_t k = r * kWave + lane;
+      if (k < nint) {
+        dep[k] = (uint16_t)d[r];
+        nxt[k] = (uint16_t)nx[r];
+      }
+    }
+    wave_sync();
+    bool active = false;
+#pragma unroll
+    for (uint32_t r = 0; r < NR; ++r) {
+      const uint32_t x = nx[r];
+      d[r] += dep[x];
+      nx[r] = nxt[x];
+      active |= nx[r] != root;
+    }
+    wave_sync();
+    if (!__ballot(active)) break;
+    if (step >= 32) {
+      if (lane == 0) raise_status(status, HF_ERR_INTERNAL);
+      break;
+    }
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < NR; ++r) {
+    const uint32_t k = r * kWave + lane;
+    if (k < nint) dep[k] = (uint16_t)d[r];
+  }
+  wave_sync();
+
+  // ---- 5a. leaf lengths, counts per length, total bits ---------------------------
+  uint64_t bits = 0;
+  uint32_t lmax = 0, lmin = 0xFFFFFFFFu;
+#pragma unroll
+  for (uint32_t r = 0; r < NR; ++r) {
+    const uint32_t e = r * kWave + lane;
+    const bool valid = e < m;
+    uint32_t l = 0;
+    if (valid) {
+      l = (uint32_t)dep[parl[e]] + 1;
+      bits += (uint64_t)lw[e] * l;
+      lmax = max(lmax, l);
+      lmin = min(lmin, l);
+      if (l > kMaxLen) l = kMaxLen;  // flagged below; keeps indexes in range
+      const uint32_t u = lu[e];
+      L.clu[u] = (uint8_t)l;
+      book.cl[(uint32_t)usym[u]] = (uint8_t)l;
+    }
+    count_lengths(l, valid, L.sh.cnt);
+  }
+  bits = wave_sum_u64(bits);
+  lmax = wave_max_u32(lmax);
+#pragma unroll
+  for (int dd = kWave / 2; dd > 0; dd >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor(lmin, dd, kWave));
+  wave_sync();
+
+  // ---- 5b. First and Entry: lane j holds length j + 1 ---------------------------
+  const uint32_t Lc = lmax > kMaxLen ? kMaxLen : lmax;
+  const uint32_t cnt = L.sh.cnt[lane + 1];
+  const uint32_t below = wave_inclusive_scan(cnt) - cnt;  // codes shorter than lane + 1
+  uint64_t fst = 0;
+  {
+    uint64_t f = 0;
+    for (int l = (int)Lc - 1; l >= 1; --l) {
+      f = (f + readlane32(cnt, (uint32_t)l) + 1) >> 1;  // cnt[l + 1]
+      if ((int)lane == l - 1) fst = f;
+    }
+  }
+  book.first[lane + 1] = fst;
+  book.entry[lane + 1] = below;
+  if (lane == 0) {
+    book.first[0] = 0;
+    book.entry[0] = 0;
+    if (lmax > kMaxLen) raise_status(status, HF_ERR_CODELEN);
+    book.info[0] = m;
+    book.info[1] = lmax;
+    book.info[2] = bits;
+    book.info[3] = lmin;
+  }
+
+  // ---- 5c. codewords: rank within each length in symbol order -------------------
+  uint32_t next = below;  // lane l-1: next rev slot of length l
+  for (uint32_t u0 = 0; u0 < m; u0 += kWave) {
+    const uint32_t u = u0 + lane;
+    const bool valid = u < m;
+    const uint32_t l = valid ? L.clu[u] : 0u;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t lv = readlane32(l, (uint32_t)leader);
+      const uint64_t mask = __ballot(valid && l == lv);
+      const uint32_t slot0 = readlane32(next, lv - 1);
+      const uint32_t e0 = readlane32(below, lv - 1);
+      const uint64_t f0 = readlane64(fst, (int)lv - 1);
+      if (valid && l == lv) {
+        const uint32_t pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
+        const uint32_t s = usym[u];
+        book.rev[pos] = s;
+        book.cw[s] = f0 + (pos - e0);
+      }
+      if (lane == lv - 1) next += (uint32_t)__popcll(mask);
+      pending &= ~mask;
+    }
+  }
+}
+
 // The whole book from hist[A] by one workgroup of NT lanes.
 template <int NT>
 __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist, const hf_codebook& book,
@@ -552,11 +834,23 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
   const uint32_t per = (A + NT - 1) / NT;
   const uint32_t s_lo = min(A, tid * per), s_hi = min(A, s_lo + per);
   uint32_t c = 0;
-  for (uint32_t s = s_lo; s < s_hi; ++s) c += (hist[s] != 0);
+  uint64_t wsum = 0;
+  for (uint32_t s = s_lo; s < s_hi; ++s) {
+    const uint32_t h = hist[s];
+    c += (h != 0);
+    wsum += h;
+  }
+  wsum = wave_sum_u64(wsum);
+  if ((tid & (kWave - 1)) == 0) L.sh.wsum[tid / kWave] = wsum;
   uint32_t m;
-  const uint32_t base = block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);
+  const uint32_t base = block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);  // (its barrier covers wsum)
+  uint64_t total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) total += L.sh.wsum[w];
 
-  if (m <= kCbLdsMaxUsed) {
+  if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
+    build_book_small<NT>(L, hist, s_lo, s_hi, base, m, book, status);
+  } else if (m <= kCbLdsMaxUsed) {
     Tree<uint16_t> t;
     t.key = L.key;
     t.iw = L.iw;
@@ -598,18 +892,13 @@ __global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict
 }
 
 // Batched stage 2: workgroup s sums stream s's per-slab counts into its
-// histogram, builds its book, then turns each slab's counts into the slab's
-// bit total (sum count * cl), its first bit (exclusive scan over the slabs)
-// and its last 32 content bits.
+// histogram and builds its book.
 constexpr int kBatchCbThreads = 256;
 
 __global__ __launch_bounds__(kBatchCbThreads) void batch_codebook_kernel(const BatchStream* __restrict__ streams) {
   __shared__ CbLds lds;
-  __shared__ uint64_t s_bits[kBatchCbThreads / kWave];
   const BatchStream bs = streams[blockIdx.x];
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
-  constexpr uint32_t NW = kBatchCbThreads / kWave;
   const uint32_t A = bs.A;
   if (bs.n == 0 && tid == 0) bs.offsets[0] = 0;
   for (uint32_t b = tid; b < A; b += kBatchCbThreads) {
@@ -620,47 +909,6 @@ __global__ __launch_bounds__(kBatchCbThreads) void batch_codebook_kernel(const B
   __threadfence_block();
   __syncthreads();
   codebook_block<kBatchCbThreads>(bs.hist, bs.book, bs.cb_ws, bs.status, lds);
-  __threadfence_block();
-  __syncthreads();
-  // per-slab bit totals (wave w handles slabs w, w + NW, ...) and last 32 bits
-  for (uint32_t g = wave; g < bs.nslabs; g += NW) {
-    const uint32_t* row = bs.part + (uint64_t)g * A;
-    uint64_t bits = 0;
-    for (uint32_t b = lane; b < A; b += kWave) bits += (uint64_t)row[b] * bs.book.cl[b];
-    bits = wave_sum_u64(bits);
-    const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
-    const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
-    const uint32_t tail = bs.sym_bytes == 1 ? range_tail<1>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw)
-                                            : range_tail<2>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw);
-    if (lane == 0) {
-      bs.slab_G[g] = bits;  // turned into the exclusive prefix below
-      bs.slab_tail[g] = tail;
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  // exclusive scan of the slab totals, 256 slabs at a time
-  uint64_t carry = 0;
-  for (uint32_t g0 = 0; g0 < bs.nslabs; g0 += kBatchCbThreads) {
-    const uint32_t g = g0 + tid;
-    const uint64_t v = g < bs.nslabs ? bs.slab_G[g] : 0;
-    uint64_t inc = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint64_t o = __shfl_up(inc, d, kWave);
-      if ((int)lane >= d) inc += o;
-    }
-    if (lane == kWave - 1) s_bits[wave] = inc;
-    __syncthreads();
-    uint64_t pre = carry, tot = 0;
-    for (uint32_t w = 0; w < NW; ++w) {
-      pre += w < wave ? s_bits[w] : 0;
-      tot += s_bits[w];
-    }
-    if (g < bs.nslabs) bs.slab_G[g] = pre + inc - v;
-    carry += tot;
-    __syncthreads();
-  }
 }
 
 hipError_t launch_batch_codebook(const BatchStream* d_streams, uint32_t nstreams, hipStream_t stream) {

@@ -197,6 +197,11 @@ __global__ __launch_bounds__(kPreThreads) void slab_bits_kernel(SlabArgs a) {
 // ---------------------------------------------------------------------------
 // Encoder: one workgroup per slab.
 // ---------------------------------------------------------------------------
+// Table entry of a code of length l <= 27: the code left-aligned in bits
+// [32 - l, 32) and f = 32 - l in bits [0, 5) (bits 5 .. 31 - l are zero);
+// 0 marks a symbol without code.
+__device__ __forceinline__ uint32_t pack_entry(uint32_t code, uint32_t l) { return (code << (32 - l)) | (32 - l); }
+
 struct EncShared {
   uint32_t wtot[kEncWaves];
   uint64_t red[kEncWaves];
@@ -228,18 +233,21 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     uint32_t ent[NS];
     uint32_t L = 0;
     bool bad = false;
+    bool full_tile = false;
     if (MODE == kModeTable && s_lo + (uint64_t)(t + 1) * T <= s_hi) {
       // whole tile inside the slab: no per-symbol branches; tab[A] = 0 catches
       // symbols outside the alphabet, a zero entry marks a symbol without code
-      uint32_t mn = 0xFFFFFFFFu;
+      uint32_t mn = 0xFFFFFFFFu, fsum = 0;
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i) {
         const uint32_t e = tab[min(raw.symbol(i), a.A)];
         ent[i] = e;
-        L += e & 31;
+        fsum += e & 31;
         mn = min(mn, e);
       }
+      L = 32 * NS - fsum;
       bad = mn == 0;
+      full_tile = true;
     } else {
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i) {
@@ -250,7 +258,7 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
             const uint32_t e = tab[min(sv, a.A)];
             bad |= e == 0;
             ent[i] = e;
-            L += e & 31;
+            L += e ? 32 - (e & 31) : 0u;
           }
         } else {
           ent[i] = 0xFFFFFFFFu;
@@ -272,23 +280,45 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
 
     // ---- reduce-merge ---------------------------------------------------------
     if (MODE == kModeTable) {
-      // at most one full word per code (<= 27 bits on <= 31 pending): the OR
-      // always issues, into this lane's dummy word when no word is complete
-      uint64_t acc = 0;
-      uint32_t nb = P & 31;  // pending bits, always < 32 between codes
+      // pend's low nb bits are this lane's bits of word wp so far (zeros for
+      // the bits of earlier lanes).  A code of len = 32 - f bits completes the
+      // word when nb >= f: the word is then bits [nb, nb + 32) of (pend:e), and
+      // what is left is bits [f, nb); otherwise all of it joins pend.  Either
+      // way the new pend is (pend:e) >> f (the shift reads only e's low 5
+      // bits, f) and the new count is (nb - f) mod 32, which is below nb
+      // exactly when a word completes (5 <= f <= 31).  At most one word
+      // completes per code (<= 27 bits on <= 31 pending); the OR always
+      // issues, into this lane's dummy word when none does.
+      uint32_t pend = 0;
+      uint32_t nb = P & 31;
       uint32_t* wp = buf + (P >> 5);
       uint32_t* const sink = dummy + tid;
+      if (full_tile) {
 #pragma unroll
-      for (uint32_t i = 0; i < NS; ++i) {
-        const uint32_t len = ent[i] & 31;
-        acc = (acc << len) | (ent[i] >> 5);
-        nb += len;  // < 59
-        const bool full = nb >= 32;
-        nb &= 31;
-        atomicOr(full ? wp : sink, (uint32_t)(acc >> nb));
-        wp += full ? 1 : 0;
+        for (uint32_t i = 0; i < NS; ++i) {
+          const uint32_t e = ent[i];
+          const uint32_t word = __builtin_amdgcn_alignbit(pend, e, nb);
+          const uint32_t nb2 = (nb - e) & 31;
+          const bool full = nb2 < nb;
+          pend = __builtin_amdgcn_alignbit(pend, e, e);
+          nb = nb2;
+          atomicOr(full ? wp : sink, word);
+          wp += full ? 1 : 0;
+        }
+      } else {
+#pragma unroll
+        for (uint32_t i = 0; i < NS; ++i) {
+          const uint32_t e = ent[i];
+          if (e == 0) continue;  // past the slab's end, or a symbol without code (flagged)
+          const uint32_t f = e & 31;
+          const uint32_t word = __builtin_amdgcn_alignbit(pend, e, nb);
+          const bool full = nb >= f;
+          pend = __builtin_amdgcn_alignbit(pend, e, f);
+          nb = (nb - f) & 31;
+          if (full) atomicOr(wp++, word);
+        }
       }
-      if (nb) atomicOr(wp, (uint32_t)(acc << (32 - nb)));
+      if (nb) atomicOr(wp, pend << (32 - nb));
     } else if (MODE == kModeGlobal) {
       uint64_t acc = 0;
       uint32_t nb = P & 31;
@@ -406,7 +436,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
       const uint32_t l = s < a.A ? a.cl[s] : 0u;
-      tab[s] = l ? (((uint32_t)a.cw[s]) << 5) | l : 0u;
+      tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
     }
   if (mode != kModeWide)
     for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
@@ -428,9 +458,40 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G);
 }
 
-// Batched stage 3: workgroup i encodes slab g of stream s for work item
-// items[i] = streams[s].item0 + g, whose first bit and predecessor tail the
-// batched codebook stage computed.  Each stream has its own alphabet,
+// Batched stage 3: bit total and last 32 content bits of slab g of stream s
+// for work item i = streams[s].item0 + g, from the slab's counts.
+__global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const BatchStream* __restrict__ streams,
+                                                                      const uint32_t* __restrict__ item_stream) {
+  __shared__ uint64_t part[kPreWaves];
+  const uint32_t item = blockIdx.x;
+  const BatchStream& bs = streams[item_stream[item]];
+  const uint32_t g = item - bs.item0;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t A = bs.A;
+  const uint32_t* row = bs.part + (uint64_t)g * A;
+  uint64_t bits = 0;
+  for (uint32_t s = tid; s < A; s += kPreThreads) bits += (uint64_t)row[s] * bs.book.cl[s];
+  bits = wave_sum_u64(bits);
+  if (lane_id() == 0) part[tid / kWave] = bits;
+  uint32_t tail = 0;
+  if (tid < kWave) {
+    const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
+    const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
+    tail = bs.sym_bytes == 1 ? range_tail<1>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw)
+                             : range_tail<2>(bs.sym, s_lo, s_hi, A, bs.book.cl, bs.book.cw);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kPreWaves; ++w) t += part[w];
+    bs.slab_bits[g] = t;
+    bs.slab_tail[g] = tail;
+  }
+}
+
+// Batched stage 4: workgroup i encodes slab g of stream s for work item
+// items[i] = streams[s].item0 + g; its first bit is the sum of the bit
+// totals of the stream's earlier slabs.  Each stream has its own alphabet,
 // symbol width and codebook.
 template <int R>
 __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchStream* __restrict__ streams,
@@ -470,16 +531,22 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
       const uint32_t l = s < a.A ? a.cl[s] : 0u;
-      tab[s] = l ? (((uint32_t)a.cw[s]) << 5) | l : 0u;
+      tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
     }
   if (mode != kModeWide)
     for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
+  uint64_t G = 0;
+  for (uint32_t k = tid; k < g; k += kEncThreads) G += bs.slab_bits[k];
+  G = wave_sum_u64(G);
+  if (lane_id() == 0) sh.red[tid / kWave] = G;
   if (tid == 0) {
     sh.tail[0] = g > 0 ? bs.slab_tail[g - 1] : 0u;
     sh.tailw = 0;
   }
-  const uint64_t G = bs.slab_G[g];
   __syncthreads();
+  G = 0;
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
   if (bs.sym_bytes == 1) {
     if (mode == kModeTable) encode_slab<R, 1, kModeTable>(a, tab, buf, dummy, sh, g, G);
     else if (mode == kModeGlobal) encode_slab<R, 1, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
@@ -609,6 +676,13 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
   e = hipGetLastError();
   timer.after(stream);
   return e;
+}
+
+hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
+                                  hipStream_t stream) {
+  if (nitems == 0) return hipSuccess;
+  batch_slab_bits_kernel<<<nitems, kPreThreads, 0, stream>>>(d_streams, d_item_stream);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,

@@ -60,10 +60,33 @@ __device__ __forceinline__ void hist_count_vec(uint32_t* sub, uint4 v, uint32_t 
   }
 }
 
+// Whole alphabet in LDS: a symbol outside it is counted in the trash bin A
+// (no branch); a non-zero trash count flags it at the end.  `subr` is the
+// lane's replica base (sub + rep) and a bin is 4 << shift bytes (R = 1 << shift).
+__device__ __forceinline__ void hist_count_all(uint32_t* subr, uint32_t s, uint32_t A, uint32_t shift) {
+  atomicAdd((uint32_t*)((char*)subr + (min(s, A) << shift)), 1u);
+}
+
+template <int SB>
+__device__ __forceinline__ void hist_count_vec_all(uint32_t* subr, uint4 v, uint32_t A, uint32_t shift) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (SB == 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) hist_count_all(subr, (w[k] >> (8 * j)) & 0xFFu, A, shift);
+    } else {
+      hist_count_all(subr, w[k] & 0xFFFFu, A, shift);
+      hist_count_all(subr, w[k] >> 16, A, shift);
+    }
+  }
+}
+
 // Counts symbols [s_lo, s_hi) into the LDS window: scalar head up to the
 // first 16-byte boundary, 16-byte vectors (four in flight per lane), scalar
-// tail.
-template <int SB>
+// tail.  ALL: the window is the whole alphabet plus a trash bin (lo = 0,
+// W = A); otherwise symbols outside [lo, lo + W) are skipped.
+template <int SB, bool ALL>
 __device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict__ sym, uint64_t s_lo,
                                            uint64_t s_hi, uint32_t lo, uint32_t W, uint32_t A, uint32_t R,
                                            uint32_t rep, bool& bad) {
@@ -76,17 +99,35 @@ __device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict
   const uint4* body = (const uint4*)((const char*)sym + (s_lo + head) * SB);
   uint64_t v = tid;
   constexpr int kUnroll = 4;
+  uint32_t* const subr = sub + rep;
+  const uint32_t shift = (uint32_t)__builtin_ctz(R) + 2;
   for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < nvec; v += kUnroll * (uint64_t)blockDim.x) {
     uint4 q[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) hist_count_vec<SB>(sub, q[u], lo, W, A, R, rep, bad);
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ALL) hist_count_vec_all<SB>(subr, q[u], A, shift);
+      else hist_count_vec<SB>(sub, q[u], lo, W, A, R, rep, bad);
+    }
   }
-  for (; v < nvec; v += blockDim.x) hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
-  for (uint64_t i = tid; i < head; i += blockDim.x) hist_count(sub, sym_load<SB>(sym, s_lo + i), lo, W, A, R, rep, bad);
-  for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x)
-    hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+  for (; v < nvec; v += blockDim.x) {
+    if (ALL) hist_count_vec_all<SB>(subr, body[v], A, shift);
+    else hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
+  }
+  for (uint64_t i = tid; i < head; i += blockDim.x) {
+    if (ALL) hist_count_all(subr, sym_load<SB>(sym, s_lo + i), A, shift);
+    else hist_count(sub, sym_load<SB>(sym, s_lo + i), lo, W, A, R, rep, bad);
+  }
+  for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x) {
+    if (ALL) hist_count_all(subr, sym_load<SB>(sym, i), A, shift);
+    else hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+  }
+}
+
+// Words of LDS a window needs: with the whole alphabet, R trash words too.
+__host__ __device__ inline uint32_t hist_window_words(uint32_t W, uint32_t A, uint32_t R) {
+  return (W == A ? W + 1 : W) * R;
 }
 
 // One launch counts bins [lo, lo + W).  Workgroup w takes the contiguous
@@ -103,7 +144,8 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
     uint32_t* __restrict__ status) {
   extern __shared__ uint32_t sub[];
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < W * R; i += blockDim.x) sub[i] = 0;
+  const bool all = lo == 0 && W == A;
+  for (uint32_t i = tid; i < hist_window_words(W, A, R); i += blockDim.x) sub[i] = 0;
   if (slab_hist && blockIdx.x == 0)
     for (uint32_t b = tid; b < A; b += blockDim.x) hist[b] = 0;
   __syncthreads();
@@ -118,7 +160,8 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
   for (uint64_t g = g0; g < g1; ++g) {
     const uint64_t s_lo = slab_begin(g, nblocks, nslabs, n);
     const uint64_t s_hi = slab_begin(g + 1, nblocks, nslabs, n);
-    hist_range<SB>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
+    if (all) hist_range<SB, true>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
+    else hist_range<SB, false>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
     if (slab_hist) {
       __syncthreads();
 #pragma unroll
@@ -142,6 +185,10 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
       if (c) atomicAdd(&hist[lo + b], c);
     }
   }
+  if (all) {
+    __syncthreads();
+    if (tid < R && sub[A * R + tid]) bad = true;
+  }
   if (bad) raise_status(status, HF_ERR_SYMBOL);
 }
 
@@ -162,28 +209,29 @@ __global__ __launch_bounds__(kHistThreads) void hist_reduce_kernel(const uint32_
   }
 }
 
-// Batched stage 1: workgroup i counts slab g of stream s for work item
-// i = streams[s].item0 + g and stores the slab's counts.  The LDS holds
-// lds_words words: as many interleaved replicas of the alphabet as fit.
+// Batched stage 1: workgroup i counts slab g of stream s for the work item
+// items[i] = streams[s].item0 + g and stores the slab's counts.  The LDS
+// holds lds_words words: as many interleaved replicas of the alphabet as fit.
 __global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const BatchStream* __restrict__ streams,
                                                                        const uint32_t* __restrict__ item_stream,
+                                                                       const uint32_t* __restrict__ items,
                                                                        uint32_t lds_words) {
   extern __shared__ uint32_t sub[];
-  const uint32_t item = blockIdx.x;
+  const uint32_t item = items[blockIdx.x];
   const uint32_t s = item_stream[item];
   const BatchStream& bs = streams[s];
   const uint32_t g = item - bs.item0;
   const uint32_t A = bs.A;
   uint32_t R = 1;
-  while (R < 16 && A * R * 2 <= lds_words) R *= 2;
+  while (R < 16 && (A + 1) * R * 2 <= lds_words) R *= 2;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < A * R; i += blockDim.x) sub[i] = 0;
+  for (uint32_t i = tid; i < (A + 1) * R; i += blockDim.x) sub[i] = 0;
   __syncthreads();
   const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
   const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
   bool bad = false;
-  if (bs.sym_bytes == 1) hist_range<1>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
-  else hist_range<2>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
+  if (bs.sym_bytes == 1) hist_range<1, true>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
+  else hist_range<2, true>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
   __syncthreads();
   uint32_t* row = bs.part + (uint64_t)g * A;
   for (uint32_t b = tid; b < A; b += blockDim.x) {
@@ -191,17 +239,20 @@ __global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const Bat
     for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
     row[b] = c;
   }
+  if (tid < R && sub[A * R + tid]) bad = true;
   if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
 }
 
-hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
-                                  uint32_t max_alphabet, hipStream_t stream) {
+uint32_t batch_hist_lds_words(uint32_t max_alphabet) { return std::max<uint32_t>(4096u, max_alphabet) + 16u; }
+
+hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream,
+                                  const uint32_t* d_items, uint32_t nitems, uint32_t lds_words,
+                                  hipStream_t stream) {
   if (nitems == 0) return hipSuccess;
-  const uint32_t lds_words = std::max<uint32_t>(4096u, max_alphabet);
   const size_t lds = (size_t)lds_words * 4;
   if (lds > (64u << 10))
     (void)hipFuncSetAttribute((const void*)batch_histogram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  batch_histogram_kernel<<<nitems, kHistThreads, lds, stream>>>(d_streams, d_item_stream, lds_words);
+  batch_histogram_kernel<<<nitems, kHistThreads, lds, stream>>>(d_streams, d_item_stream, d_items, lds_words);
   return hipGetLastError();
 }
 
@@ -223,10 +274,10 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStrea
 // per CU); alphabets whose single copy needs more use one copy of up to
 // 32768 bins (128 KiB) and several passes for larger alphabets.
 static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
-  const uint32_t budget = 16u << 10;
-  if (A * 4u <= budget) {
+  const uint32_t budget = (16u << 10) + 64u;  // 16 KiB plus the trash bins
+  if ((A + 1) * 4u <= budget) {
     uint32_t r = 1;
-    while (r < 16 && A * 4u * (r * 2) <= budget) r *= 2;
+    while (r < 16 && (A + 1) * 4u * (r * 2) <= budget) r *= 2;
     *W = A;
     *R = r;
   } else {
@@ -249,7 +300,7 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
                             const KernelTimer& timer) {
   uint32_t W, R;
   hist_plan(A, &W, &R);
-  const size_t lds = (size_t)W * R * sizeof(uint32_t);
+  const size_t lds = (size_t)hist_window_words(W, A, R) * sizeof(uint32_t);
   const uint64_t nblocks = (n + kSlabBlock - 1) / kSlabBlock;
   hipError_t e;
   if (!slab_hist && A <= kSlabHistMaxAlphabet) {
@@ -266,7 +317,7 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
   } else {
     e = launch_fill_u32(hist, A, 0u, stream);
     if (e != hipSuccess) return e;
-    const uint64_t wgs_per_cu = lds <= (16u << 10) ? 8 : (lds <= (64u << 10) ? 2 : 1);
+    const uint64_t wgs_per_cu = lds <= (16u << 10) + 64u ? 8 : (lds <= (64u << 10) ? 2 : 1);
     grid = std::min<uint64_t>((uint64_t)num_cus * wgs_per_cu, (nblocks + 3) / 4);
     if (grid < 1) grid = 1;
     nslabs = (uint32_t)grid;

@@ -15,7 +15,7 @@ constexpr int kEncWaves = kEncThreads / 64;
 constexpr int kEncMinR = 1;
 constexpr int kEncMaxR = 6;
 constexpr int kEncDefaultR = 4;
-constexpr uint32_t kPackedMaxLen = 27;        // cw << 5 | cl fits 32 bits
+constexpr uint32_t kPackedMaxLen = 27;        // a left-aligned code plus 5 bits of 32 - cl fit 32 bits
 
 // Slab partition shared by the histogram and the encoder: slab g of S
 // covers blocks [g*nb/S, (g+1)*nb/S) of kSlabBlock symbols, nb = ceil(n / kSlabBlock).
@@ -92,7 +92,7 @@ struct BatchStream {
   uint32_t* hist;       // [A]
   hf_codebook book;
   char* cb_ws;          // codebook tree when more than kCbLdsMaxUsed symbols are used
-  uint64_t* slab_G;     // [nslabs] first bit of each slab
+  uint64_t* slab_bits;  // [nslabs] content bits of each slab
   uint32_t* slab_tail;  // [nslabs] last 32 content bits of each slab
   uint32_t* out;
   uint64_t cap_words;
@@ -100,10 +100,15 @@ struct BatchStream {
   uint32_t* status;
 };
 
-hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
-                                  uint32_t max_alphabet, hipStream_t stream);
+// Histogram LDS words for a batch group whose alphabets are at most A.
+uint32_t batch_hist_lds_words(uint32_t max_alphabet);
+hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream,
+                                  const uint32_t* d_items, uint32_t nitems, uint32_t lds_words,
+                                  hipStream_t stream);
 hipError_t launch_batch_codebook(const BatchStream* d_streams, uint32_t nstreams, hipStream_t stream);
-// r in {3, 4, 5} (others run as 4).
+hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
+                                  hipStream_t stream);
+// r in {3, 4, 5} (others run as 4); every item's alphabet is at most max_alphabet.
 hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
                                hipStream_t stream);

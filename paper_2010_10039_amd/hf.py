@@ -206,6 +206,8 @@ def hf_build_codebook(hist: torch.Tensor, book: Codebook | None = None, ws: torc
         book = Codebook.empty(hist.numel(), hist.device)
     if status is None:
         status = new_status(hist.device)
+    if ws is None:  # alphabets above 4096 build the tree in device memory
+        ws = new_workspace(1, hist.numel(), device=hist.device)
     s = book.struct()
     _check(_lib.hf_build_codebook(_ptr(hist), ctypes.byref(s), _ptr(ws), 0 if ws is None else ws.numel(),
                                   _ptr(status), _stream()), "hf_build_codebook")

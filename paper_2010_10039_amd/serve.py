@@ -109,16 +109,28 @@ class Request:
         return None if self.done is None else self.done - self.arrival
 
 
-def admit(queue: list, free_slots: int, max_batch: int, reserve) -> list:
+def admit(queue: list, free_slots: int, max_batch: int, reserve, solo=lambda r: False,
+          max_batch_bytes: int | None = None) -> list:
     """Takes requests from the head of `queue` (FIFO, no overtaking) while
-    `reserve(req)` succeeds, at most max_batch of them, and only if a slot
-    is free.  `reserve` returns False when the arena cannot hold the
-    request now.  Returns the admitted requests (removed from the queue)."""
-    if free_slots <= 0:
+    `reserve(req)` succeeds, and only if a slot is free.  A request for
+    which solo(req) holds is launched alone; otherwise consecutive
+    non-solo requests are gathered, at most max_batch of them and, past the
+    first, at most max_batch_bytes of input.  `reserve` returns False when
+    the arena cannot hold the request now.  Returns the admitted requests
+    (removed from the queue)."""
+    if free_slots <= 0 or not queue:
         return []
-    out = []
-    while queue and len(out) < max_batch and reserve(queue[0]):
+    if solo(queue[0]):
+        return [queue.pop(0)] if reserve(queue[0]) else []
+    out, nbytes = [], 0
+    while queue and len(out) < max_batch and not solo(queue[0]):
+        r = queue[0]
+        if out and max_batch_bytes is not None and nbytes + r.nbytes > max_batch_bytes:
+            break
+        if not reserve(r):
+            break
         out.append(queue.pop(0))
+        nbytes += r.nbytes
     return out
 
 
@@ -133,6 +145,7 @@ class Batch:
 class ServeLoop:
     """The queue / admission / completion loop, independent of the device.
 
+    executor.solo(req) -> True if the request is launched alone
     executor.footprint(req) -> own bytes (kept until release)
     executor.batch_bytes(reqs) -> shared workspace bytes of a batch
     executor.launch(batch) -> handle (asynchronous; batch.ws is its workspace range)
@@ -141,8 +154,9 @@ class ServeLoop:
     """
 
     def __init__(self, executor, capacity: int, slots: int = 3, max_batch: int = 64,
-                 keep_results: bool = False):
+                 keep_results: bool = False, max_batch_bytes: int | None = None):
         self.ex = executor
+        self.max_batch_bytes = max_batch_bytes
         self.arena = Arena(capacity)
         self.slots = [None] * slots
         self.max_batch = max_batch
@@ -205,7 +219,7 @@ class ServeLoop:
         free = [i for i, b in enumerate(self.slots) if b is None]
         if not free or not self.queue:
             return None
-        reqs = admit(self.queue, len(free), self.max_batch, self._reserve)
+        reqs = admit(self.queue, len(free), self.max_batch, self._reserve, self.ex.solo, self.max_batch_bytes)
         ws = None
         while reqs:
             wsb = self.ex.batch_bytes(reqs)
@@ -310,7 +324,8 @@ class GpuExecutor:
     region starts with one status word per request (in launch order: the
     batched requests first)."""
 
-    def __init__(self, capacity: int, slots: int, max_batch: int, device="cuda", use_batch: bool = True):
+    def __init__(self, capacity: int, slots: int, max_batch: int, device="cuda", use_batch: bool = True,
+                 solo_bytes: int = 32 << 20):
         import torch
 
         from . import hf
@@ -318,16 +333,22 @@ class GpuExecutor:
         assert max_batch * 4 <= ALIGN
         self.torch, self.hf = torch, hf
         self.use_batch = use_batch
+        self.solo_bytes = solo_bytes
         self.buf = torch.empty(capacity, dtype=torch.uint8, device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         self.host_status = [torch.zeros(max_batch, dtype=torch.int32).pin_memory() for _ in range(slots)]
         self._ws_cache: dict = {}
 
     # sizes ---------------------------------------------------------------
+    def solo(self, req: Request) -> bool:
+        """Large requests (or large alphabets) fill the device by
+        themselves: they run alone, with plain calls, on their own stream."""
+        return not self.use_batch or not req.batched or req.nbytes >= self.solo_bytes
+
     def batched(self, req: Request) -> bool:
         """Whether the request goes through hf_encode_batch (else plain
         per-request calls)."""
-        return self.use_batch and req.batched
+        return not self.solo(req)
 
     def _single_desc_ws(self, req: Request) -> int:
         key = (req.n, req.sym_bytes, req.alphabet, req.chunk, req.r)
@@ -422,13 +443,13 @@ class GpuExecutor:
 
 
 def serve(requests: list, capacity: int, slots: int = 3, max_batch: int = 32, keep_results: bool = False,
-          device="cuda", use_batch: bool = True):
+          device="cuda", use_batch: bool = True, solo_bytes: int = 32 << 20, max_batch_bytes: int = 64 << 20):
     """Serves `requests` (sorted by arrival, each with .sym on the device)
     in real time; returns the ServeLoop (finished requests with their
     latencies, results when kept).  use_batch=False, slots=1, max_batch=1
     is the one-request-at-a-time server with plain launches."""
-    ex = GpuExecutor(capacity, slots, max_batch, device, use_batch)
-    loop = ServeLoop(ex, capacity, slots, max_batch, keep_results)
+    ex = GpuExecutor(capacity, slots, max_batch, device, use_batch, solo_bytes)
+    loop = ServeLoop(ex, capacity, slots, max_batch, keep_results, max_batch_bytes)
     t0 = time.perf_counter()
     loop.run(requests, clock=lambda: time.perf_counter() - t0)
     return loop

@@ -111,12 +111,13 @@ def test_batch_equals_single_stream_path():
     enc = run_batch(xs, alph)
     for i, (x, A) in enumerate(zip(xs, alph)):
         d = _dev(x)
-        hist = hf.hf_histogram(d, A)
-        book = hf.hf_build_codebook(hist)
+        ws = hf.new_workspace(x.size, A)
+        status = hf.new_status()
+        hist = hf.hf_histogram(d, A, ws=ws, status=status)
+        book = hf.hf_build_codebook(hist, ws=ws, status=status)
         out = torch.empty(hf.hf_bound_words(x.size, A), dtype=torch.int32, device="cuda")
         offs = torch.empty((x.size + 4095) // 4096 + 1, dtype=torch.int64, device="cuda")
-        status = hf.new_status()
-        hf.hf_encode(d, book, 4096, 0, out, offs, hf.new_workspace(x.size, A), status)
+        hf.hf_encode(d, book, 4096, 0, out, offs, ws, status)
         assert hf.read_status(status) == 0
         nw = (int(offs[-1].item()) + 31) // 32
         assert torch.equal(enc.offsets[i], offs)
@@ -164,6 +165,8 @@ def test_batch_full_size_sample():
     compared with the oracle on every 8th stream."""
     syms, alph = W.batched_streams(64, seed=1000, device="cuda")
     enc = hf.BatchEncoder(syms, alph, 4096, 0)
+    for o in enc.outs:
+        o.fill_(SENTINEL)
     enc.run()
     torch.cuda.synchronize()
     assert np.all(enc.status.cpu().numpy() == 0)

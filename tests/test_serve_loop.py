@@ -59,13 +59,40 @@ def test_arena_double_free_is_caught():
         a.release(off, 300)
 
 
+class _R:
+    def __init__(self, name, nbytes=1):
+        self.name, self.nbytes = name, nbytes
+
+    def __repr__(self):
+        return self.name
+
+
 def test_admit_is_fifo_without_overtaking():
-    q = ["big", "small", "small2"]
-    got = S.admit(q, 1, 8, lambda r: r != "big")
-    assert got == [] and q == ["big", "small", "small2"]
+    q = [_R("big"), _R("small"), _R("small2")]
+    got = S.admit(q, 1, 8, lambda r: r.name != "big")
+    assert got == [] and [r.name for r in q] == ["big", "small", "small2"]
     got = S.admit(q, 1, 2, lambda r: True)
-    assert got == ["big", "small"] and q == ["small2"]
+    assert [r.name for r in got] == ["big", "small"] and [r.name for r in q] == ["small2"]
     assert S.admit(q, 0, 8, lambda r: True) == []
+
+
+def test_admit_runs_solo_requests_alone_and_caps_batch_bytes():
+    class R:
+        def __init__(self, name, nbytes, solo=False):
+            self.name, self.nbytes, self.is_solo = name, nbytes, solo
+
+    q = [R("a", 10), R("b", 10), R("big", 10, True), R("c", 10)]
+    solo = lambda r: r.is_solo  # noqa: E731
+    got = S.admit(q, 1, 8, lambda r: True, solo)
+    assert [r.name for r in got] == ["a", "b"]  # stops before the solo one
+    got = S.admit(q, 1, 8, lambda r: True, solo)
+    assert [r.name for r in got] == ["big"]
+    q = [R("x", 60), R("y", 30), R("z", 10), R("w", 5)]
+    got = S.admit(q, 1, 8, lambda r: True, solo, max_batch_bytes=100)
+    assert [r.name for r in got] == ["x", "y", "z"]
+    q = [R("huge", 500), R("t", 1)]
+    got = S.admit(q, 1, 8, lambda r: True, solo, max_batch_bytes=100)
+    assert [r.name for r in got] == ["huge"]  # the first always goes
 
 
 def test_percentile_nearest_rank():
@@ -96,6 +123,9 @@ class FakeExecutor:
         self.launches = []
         self.max_inflight = 0
         self.inflight = set()
+
+    def solo(self, req):
+        return not req.batched
 
     def footprint(self, req):
         return req.nbytes // 2 + 1000
