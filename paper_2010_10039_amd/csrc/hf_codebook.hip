@@ -593,22 +593,35 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   __syncthreads();
 
   // ---- 2. rank sort: wave w ranks keys [64w, 64w + 64) against all keys -------
+  // Keys are in compact-index order, so the rank of e by (weight, index) is
+  // #{j < e: w_j <= w_e} + #{j > e: w_j < w_e}, all on 32-bit weights.
   if (wave < kSmallUsed / kWave) {
     const uint32_t e = wave * kWave + lane;
-    const uint64_t k = e < m ? key[e] : ~0ull;
-    uint64_t K[kSmallUsed / kWave];
+    const uint32_t we = e < m ? (uint32_t)(key[e] >> 16) : kInf32;
+    uint32_t W[kSmallUsed / kWave];
 #pragma unroll
-    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r) K[r] = r * kWave + lane < m ? key[r * kWave + lane] : ~0ull;
-    uint32_t rank = 0;
+    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r)
+      W[r] = r * kWave + lane < m ? (uint32_t)(key[r * kWave + lane] >> 16) : kInf32;
+    uint32_t acc[4] = {0, 0, 0, 0};
+    for (uint32_t r = 0; r < kSmallUsed / kWave && r * kWave < m; ++r) {
+      uint32_t Wr = W[0];
 #pragma unroll
-    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r) {
-      const uint32_t nl = m > r * kWave ? min((uint32_t)kWave, m - r * kWave) : 0u;
-#pragma unroll 4
-      for (uint32_t l = 0; l < nl; ++l) rank += readlane64(K[r], (int)l) < k;
+      for (uint32_t q = 1; q < kSmallUsed / kWave; ++q) Wr = r == q ? W[q] : Wr;
+      if (r < wave) {
+#pragma unroll
+        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) <= we;
+      } else if (r > wave) {
+#pragma unroll
+        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) < we;
+      } else {
+#pragma unroll
+        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) < we + (lane > l ? 1u : 0u);
+      }
     }
+    const uint32_t rank = acc[0] + acc[1] + acc[2] + acc[3];
     if (e < m) {
-      lw[rank] = (uint32_t)(k >> 16);
-      lu[rank] = (uint16_t)(k & 0xFFFFu);
+      lw[rank] = we;
+      lu[rank] = (uint16_t)e;
     }
   }
   __syncthreads();
@@ -650,10 +663,19 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
       const uint32_t total = a + b, pairs = total >> 1;
       uint32_t last_leaf, last_int;
       if (a <= (uint32_t)kWave && b <= (uint32_t)kWave) {
-        uint32_t cl_ = 0, ci = 0;
-        for (uint32_t q = 0; q < b; ++q) cl_ += readlane32(RI, q) < RL;   // internals lighter than my leaf
-        for (uint32_t j = 0; j < a; ++j) ci += readlane32(RL, j) <= RI;   // leaves no heavier than my node
-        const uint32_t pl = lane + cl_, pi = lane + ci;
+        // internals lighter than my leaf (RI is INF past b), leaves of the
+        // run no heavier than my node (RLa is INF past a); 8 at a time
+        const uint32_t RLa = lane < a ? RL : kInf32;
+        uint32_t c[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
+        for (uint32_t q0 = 0; q0 < b; q0 += 8) {
+#pragma unroll
+          for (uint32_t j = 0; j < 8; ++j) c[j & 3] += readlane32(RI, q0 + j) < RL;
+        }
+        for (uint32_t j0 = 0; j0 < a; j0 += 8) {
+#pragma unroll
+          for (uint32_t j = 0; j < 8; ++j) d[j & 3] += readlane32(RLa, j0 + j) <= RI;
+        }
+        const uint32_t pl = lane + c[0] + c[1] + c[2] + c[3], pi = lane + d[0] + d[1] + d[2] + d[3];
         if (lane < a && pl < 2 * pairs) {
           parl[lc + lane] = (uint16_t)(it + (pl >> 1));
           atomicAdd(&iw[it + (pl >> 1)], RL);
@@ -755,10 +777,8 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
 #pragma unroll
   for (uint32_t r = 0; r < NR; ++r) {
     const uint32_t e = r * kWave + lane;
-    const bool valid = e < m;
-    uint32_t l = 0;
-    if (valid) {
-      l = (uint32_t)dep[parl[e]] + 1;
+    if (e < m) {
+      uint32_t l = (uint32_t)dep[parl[e]] + 1;
       bits += (uint64_t)lw[e] * l;
       lmax = max(lmax, l);
       lmin = min(lmin, l);
@@ -766,8 +786,8 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
       const uint32_t u = lu[e];
       L.clu[u] = (uint8_t)l;
       book.cl[(uint32_t)usym[u]] = (uint8_t)l;
+      atomicAdd(&L.sh.cnt[l], 1u);
     }
-    count_lengths(l, valid, L.sh.cnt);
   }
   bits = wave_sum_u64(bits);
   lmax = wave_max_u32(lmax);
@@ -776,19 +796,32 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   wave_sync();
 
   // ---- 5b. First and Entry: lane j holds length j + 1 ---------------------------
+  // first[l] = ceil((first[l+1] + cnt[l+1]) / 2) with first[Lc] = 0 unrolls to
+  // ceil(S / 2^(Lc-l)), S = sum over k > l of cnt[k] 2^(Lc-k) (nested ceilings
+  // of halvings compose); S < 2^53 for n < 2^32.
   const uint32_t Lc = lmax > kMaxLen ? kMaxLen : lmax;
-  const uint32_t cnt = L.sh.cnt[lane + 1];
-  const uint32_t below = wave_inclusive_scan(cnt) - cnt;  // codes shorter than lane + 1
+  const uint32_t len = lane + 1;
+  const uint32_t cnt = L.sh.cnt[len];
+  const uint32_t below = wave_inclusive_scan(cnt) - cnt;  // codes shorter than len
   uint64_t fst = 0;
   {
-    uint64_t f = 0;
-    for (int l = (int)Lc - 1; l >= 1; --l) {
-      f = (f + readlane32(cnt, (uint32_t)l) + 1) >> 1;  // cnt[l + 1]
-      if ((int)lane == l - 1) fst = f;
+    // suffix sum over lanes j > lane of cnt[j + 1] * 2^(Lc - j - 1)
+    const uint64_t term = (len <= Lc) ? ((uint64_t)cnt << (Lc - len)) : 0ull;
+    uint64_t suf = term;
+#pragma unroll
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+      const uint64_t o = __shfl_down(suf, dd, kWave);
+      if ((int)lane + dd < kWave) suf += o;
     }
+    const uint64_t S = suf - term;
+    if (len < Lc) fst = (S + (1ull << (Lc - len)) - 1) >> (Lc - len);
   }
-  book.first[lane + 1] = fst;
-  book.entry[lane + 1] = below;
+  book.first[len] = fst;
+  book.entry[len] = below;
+  uint64_t* fl = (uint64_t*)L.mw;        // [65] first, by length
+  uint32_t* el = (uint32_t*)(fl + 65);  // [65] entry, by length
+  fl[len] = fst;
+  el[len] = below;
   if (lane == 0) {
     book.first[0] = 0;
     book.entry[0] = 0;
@@ -798,6 +831,7 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
     book.info[2] = bits;
     book.info[3] = lmin;
   }
+  wave_sync();
 
   // ---- 5c. codewords: rank within each length in symbol order -------------------
   uint32_t next = below;  // lane l-1: next rev slot of length l
@@ -805,22 +839,21 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
     const uint32_t u = u0 + lane;
     const bool valid = u < m;
     const uint32_t l = valid ? L.clu[u] : 0u;
+    uint32_t pos = 0;
     uint64_t pending = __ballot(valid);
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
       const uint32_t lv = readlane32(l, (uint32_t)leader);
       const uint64_t mask = __ballot(valid && l == lv);
       const uint32_t slot0 = readlane32(next, lv - 1);
-      const uint32_t e0 = readlane32(below, lv - 1);
-      const uint64_t f0 = readlane64(fst, (int)lv - 1);
-      if (valid && l == lv) {
-        const uint32_t pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
-        const uint32_t s = usym[u];
-        book.rev[pos] = s;
-        book.cw[s] = f0 + (pos - e0);
-      }
+      if (valid && l == lv) pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
       if (lane == lv - 1) next += (uint32_t)__popcll(mask);
       pending &= ~mask;
+    }
+    if (valid) {
+      const uint32_t s = usym[u];
+      book.rev[pos] = s;
+      book.cw[s] = fl[l] + (pos - el[l]);
     }
   }
 }

@@ -210,6 +210,28 @@ def _hist_cases():
     cases["uniform65536"] = W.skewed_histogram(65536, 65536 * 3, kind="uniform")
     h = rng.integers(0, 3, size=8192).astype(np.uint32) * rng.integers(1, 1 << 20, size=8192).astype(np.uint32)
     cases["sparse8192"] = h
+    # books of up to 256 used symbols take the 32-bit register path: used
+    # counts around every 64-element register boundary, with geometric,
+    # random and tied counts, scattered over the alphabet
+    for mm in (2, 3, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257):
+        for kind in ("geom", "rand", "ties"):
+            h = np.zeros(4096 if mm > 200 else 1024, np.uint32)
+            pos = np.sort(rng.choice(h.size, size=mm, replace=False))
+            if kind == "geom":
+                v = np.maximum(1, (1e9 * 0.93 ** np.arange(mm))).astype(np.uint32)
+                rng.shuffle(v)
+            elif kind == "rand":
+                v = rng.integers(1, 1 << 24, size=mm).astype(np.uint32)
+            else:
+                v = rng.choice(np.array([1, 2, 2, 5, 5, 5], np.uint32), size=mm)
+            h[pos] = v
+            cases[f"m{mm}_{kind}"] = h
+    # the sum of counts just below / at 2^32 - 1 (register path / general path)
+    h = np.zeros(1024, np.uint32); h[:200] = 1; h[500] = 0xFFFFFFFE - 200 - 7; h[501:508] = 1
+    assert int(h.sum(dtype=np.uint64)) == 0xFFFFFFFE
+    cases["total_2^32-2"] = h
+    h = h.copy(); h[502] += 1
+    cases["total_2^32-1"] = h
     return cases
 
 
