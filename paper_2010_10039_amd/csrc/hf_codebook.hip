@@ -13,8 +13,8 @@
 //  1. compaction: used symbols in ascending symbol order get compact index u;
 //     unused symbols receive cl = cw = 0 at once;
 //  2. sort leaves by (count, u) -- u preserves symbol order -- on 48-bit keys
-//     (count << 16 | u): rank sort up to 512 used symbols, bitonic network
-//     above; the paper sorts with Thrust;
+//     (count << 16 | u): rank sort up to 512 used symbols, a stable LSD radix
+//     sort on the count above (4 bits a pass); the paper sorts with Thrust;
 //  3. GenerateCL: rounds of the parallel two-queue construction.  t = sum of
 //     the two lightest available nodes (leaf before internal on equal
 //     weight); every unconsumed leaf with weight <= t and every queued
@@ -92,8 +92,14 @@ struct Tree {
 
 constexpr int kCbMaxWaves = 16;
 
+// Above this many used symbols a round's runs are long enough that the whole
+// workgroup merges them (three barriers a round) instead of one wave.
+constexpr uint32_t kOneWaveRoundsMax = 1024;
+
 struct Shared {
   uint64_t wsum[kCbMaxWaves];
+  uint32_t wmax[kCbMaxWaves];
+  uint32_t rcnt[kCbMaxWaves * 16];  // radix sort: digit counts, then offsets, per wave
   uint32_t wtot[kCbMaxWaves];
   uint32_t cnt[kMaxLen + 1];
   uint32_t cntw[kCbMaxWaves][kMaxLen + 1];
@@ -227,30 +233,102 @@ __device__ __forceinline__ void rounds_one_wave(const Tree<IdT>& t, uint32_t m, 
   }
 }
 
+// Compaction in symbol order, NT symbols at a time (coalesced reads): used
+// symbol s gets compact index u (its rank among used symbols), key[u] =
+// count << 16 | u and usym[u] = s; unused symbols get cl = cw = 0.
+template <int NT, typename IdT>
+__device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint32_t A, uint64_t* key, IdT* usym,
+                                        const hf_codebook& book, uint32_t* wtot) {
+  uint32_t run = 0;
+  for (uint32_t c0 = 0; c0 < A; c0 += NT) {
+    const uint32_t s = c0 + threadIdx.x;
+    const uint32_t h = s < A ? hist[s] : 0u;
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan<NT / kWave>(h != 0, wtot, &tot);
+    if (h) {
+      const uint32_t u = run + pre;
+      key[u] = ((uint64_t)h << 16) | u;
+      usym[u] = (IdT)s;
+    } else if (s < A) {
+      book.cl[s] = 0;
+      book.cw[s] = 0;
+    }
+    run += tot;
+    __syncthreads();  // wtot is reused by the next chunk
+  }
+}
+
+// Stable LSD radix sort of key[0, m) (count << 16 | u, in u order) by the
+// 32-bit count, 4 bits a pass, as many passes as the largest count needs;
+// tmp[0, m) is the other buffer.  Wave w owns the contiguous segment w of the
+// keys: it counts its digits (LDS atomics), a workgroup scan turns the
+// counts into offsets in (digit, wave) order, and the wave scatters its
+// segment 64 keys at a time, ranking equal digits by lane order (a 4-ballot
+// match), so equal counts keep their order.
+template <int NT>
+__device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, uint32_t m, uint32_t wmax,
+                                                Shared& sh) {
+  constexpr uint32_t NW = NT / kWave;
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  uint32_t passes = 0;
+  while (passes < 8 && (wmax >> (4 * passes)) != 0) ++passes;
+  const uint32_t seg = (m + NW - 1) / NW;
+  const uint32_t s0 = min(m, wave * seg), s1 = min(m, s0 + seg);
+  uint64_t* src = key;
+  uint64_t* dst = tmp;
+  uint32_t* cnt = sh.rcnt;
+  for (uint32_t p = 0; p < passes; ++p) {
+    const uint32_t shift = 16 + 4 * p;
+    for (uint32_t i = tid; i < NW * 16; i += NT) cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t i = s0 + lane; i < s1; i += kWave) atomicAdd(&cnt[wave * 16 + ((uint32_t)(src[i] >> shift) & 15)], 1u);
+    __syncthreads();
+    // offsets in (digit, wave) order: thread d * NW + w takes counter (w, d)
+    const uint32_t w_of = tid % NW, d_of = tid / NW;
+    const uint32_t v = tid < NW * 16 ? cnt[w_of * 16 + d_of] : 0u;
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan<NW>(v, sh.wtot, &tot);
+    __syncthreads();
+    if (tid < NW * 16) cnt[w_of * 16 + d_of] = pre;
+    __syncthreads();
+    for (uint32_t b = s0; b < s1; b += kWave) {
+      const uint32_t i = b + lane;
+      const bool valid = i < s1;
+      const uint64_t k = valid ? src[i] : 0ull;
+      const uint32_t d = (uint32_t)(k >> shift) & 15;
+      uint64_t match = __ballot(valid);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool bit = (d >> q) & 1;
+        const uint64_t mb = __ballot(valid && bit);
+        match &= bit ? mb : ~mb;
+      }
+      const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
+      if (valid) dst[cnt[wave * 16 + d] + rank] = k;
+      if (valid && rank == 0) atomicAdd(&cnt[wave * 16 + d], (uint32_t)__popcll(match));
+      wave_sync();  // this wave's next group reads the advanced offsets
+    }
+    __syncthreads();
+    uint64_t* t2 = src;
+    src = dst;
+    dst = t2;
+  }
+  if (src != key) {
+    for (uint32_t i = tid; i < m; i += NT) key[i] = src[i];
+  }
+}
+
 template <typename IdT, int NT>
 __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
-                                           uint32_t A, uint32_t s_lo, uint32_t s_hi, uint32_t base,
-                                           uint32_t m, const hf_codebook& book, uint32_t* status) {
+                                           uint32_t A, uint32_t m, uint32_t wmax, const hf_codebook& book,
+                                           uint32_t* status) {
   constexpr int NW = NT / kWave;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
 
   // ---- 1. compaction -----------------------------------------------------
-  {
-    uint32_t u = base;
-    for (uint32_t s = s_lo; s < s_hi; ++s) {
-      const uint32_t h = hist[s];
-      if (h) {
-        t.key[u] = ((uint64_t)h << 16) | u;
-        t.usym[u] = (IdT)s;
-        ++u;
-      } else {
-        book.cl[s] = 0;
-        book.cw[s] = 0;
-      }
-    }
-  }
+  compact<NT>(hist, A, t.key, t.usym, book, sh.wtot);
   const uint32_t P = pow2_ceil(m > 0 ? m : 1);
   for (uint32_t l = tid; l <= kMaxLen; l += NT) sh.cnt[l] = 0;
   if (tid == 0) {
@@ -300,29 +378,13 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     __syncthreads();
     for (uint32_t i = tid; i < m; i += NT) t.key[i] = t.mw[i];
   } else {
-    for (uint32_t i = m + tid; i < P; i += NT) t.key[i] = ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tid; i < P / 2; i += NT) {
-          const uint32_t l = 2 * j * (i / j) + (i & (j - 1));
-          const uint32_t r = l + j;
-          const bool up = (l & k) == 0;
-          const uint64_t x = t.key[l], y = t.key[r];
-          if ((x > y) == up) {
-            t.key[l] = y;
-            t.key[r] = x;
-          }
-        }
-        __syncthreads();
-      }
-    }
+    radix_sort_keys<NT>(t.key, t.mw, m, wmax, sh);
   }
   __syncthreads();
 
   // ---- 3. GenerateCL rounds ------------------------------------------------
-  if constexpr (sizeof(IdT) == 2) {
-    // tree in LDS: one wave runs the rounds
+  if (sizeof(IdT) == 2 && m <= kOneWaveRoundsMax) {
+    // tree in LDS, short runs: one wave runs the rounds
     if (wave == 0) rounds_one_wave(t, m, status);
     __syncthreads();
   } else {
@@ -557,8 +619,7 @@ __device__ __forceinline__ uint32_t readlane32(uint32_t v, uint32_t l) {
 }
 
 template <int NT>
-__device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __restrict__ hist, uint32_t s_lo,
-                                                 uint32_t s_hi, uint32_t base, uint32_t m,
+__device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __restrict__ hist, uint32_t m,
                                                  const hf_codebook& book, uint32_t* status) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
@@ -574,20 +635,7 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   uint16_t* nxt = L.par + 3 * kSmallUsed;   // [m-1] jump target
 
   // ---- 1. compaction ---------------------------------------------------------
-  {
-    uint32_t u = base;
-    for (uint32_t s = s_lo; s < s_hi; ++s) {
-      const uint32_t h = hist[s];
-      if (h) {
-        key[u] = ((uint64_t)h << 16) | u;
-        usym[u] = (uint16_t)s;
-        ++u;
-      } else {
-        book.cl[s] = 0;
-        book.cw[s] = 0;
-      }
-    }
-  }
+  compact<NT>(hist, book.alphabet, key, usym, book, L.sh.wtot);
   for (uint32_t i = tid; i < kSmallUsed; i += NT) iw[i] = 0;
   for (uint32_t l = tid; l <= kMaxLen; l += NT) L.sh.cnt[l] = 0;
   __syncthreads();
@@ -864,25 +912,33 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
                                                char* ws, uint32_t* status, CbLds& L) {
   const uint32_t A = book.alphabet;
   const uint32_t tid = threadIdx.x;
-  const uint32_t per = (A + NT - 1) / NT;
-  const uint32_t s_lo = min(A, tid * per), s_hi = min(A, s_lo + per);
-  uint32_t c = 0;
+  uint32_t c = 0, hmax = 0;
   uint64_t wsum = 0;
-  for (uint32_t s = s_lo; s < s_hi; ++s) {
+  for (uint32_t s = tid; s < A; s += NT) {
     const uint32_t h = hist[s];
     c += (h != 0);
     wsum += h;
+    hmax = max(hmax, h);
   }
   wsum = wave_sum_u64(wsum);
-  if ((tid & (kWave - 1)) == 0) L.sh.wsum[tid / kWave] = wsum;
+  hmax = wave_max_u32(hmax);
+  if ((tid & (kWave - 1)) == 0) {
+    L.sh.wsum[tid / kWave] = wsum;
+    L.sh.wmax[tid / kWave] = hmax;
+  }
   uint32_t m;
-  const uint32_t base = block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);  // (its barrier covers wsum)
+  (void)block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);  // (its barrier covers wsum and wmax)
   uint64_t total = 0;
+  uint32_t wmax = 0;
 #pragma unroll
-  for (int w = 0; w < NT / kWave; ++w) total += L.sh.wsum[w];
+  for (int w = 0; w < NT / kWave; ++w) {
+    total += L.sh.wsum[w];
+    wmax = max(wmax, L.sh.wmax[w]);
+  }
+  __syncthreads();  // wtot is reused by the compaction
 
   if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
-    build_book_small<NT>(L, hist, s_lo, s_hi, base, m, book, status);
+    build_book_small<NT>(L, hist, m, book, status);
   } else if (m <= kCbLdsMaxUsed) {
     Tree<uint16_t> t;
     t.key = L.key;
@@ -896,7 +952,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = t.dA + kCbLdsMaxUsed;
     t.nA = t.dB + kCbLdsMaxUsed;
     t.nB = t.nA + kCbLdsMaxUsed;
-    build_book<uint16_t, NT>(t, L.sh, hist, A, s_lo, s_hi, base, m, book, status);
+    build_book<uint16_t, NT>(t, L.sh, hist, A, m, wmax, book, status);
   } else {
     const GlobalLayout G = global_layout(A);
     Tree<uint32_t> t;
@@ -911,7 +967,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = (uint16_t*)(ws + G.dB);
     t.nA = (uint32_t*)(ws + G.nA);
     t.nB = (uint32_t*)(ws + G.nB);
-    build_book<uint32_t, NT>(t, L.sh, hist, A, s_lo, s_hi, base, m, book, status);
+    build_book<uint32_t, NT>(t, L.sh, hist, A, m, wmax, book, status);
   }
 }
 
@@ -957,10 +1013,7 @@ hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* 
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
   (void)ws_bytes;
   timer.before(stream);
-  if (book.alphabet <= kCbLdsMaxUsed)
-    codebook_kernel<256><<<1, 256, 0, stream>>>(hist, book, (char*)ws, status);
-  else
-    codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, (char*)ws, status);
+  codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, (char*)ws, status);
   hipError_t e = hipGetLastError();
   timer.after(stream);
   return e;

@@ -226,6 +226,10 @@ def _hist_cases():
                 v = rng.choice(np.array([1, 2, 2, 5, 5, 5], np.uint32), size=mm)
             h[pos] = v
             cases[f"m{mm}_{kind}"] = h
+    # 1024 < m <= 4096: tree in LDS, rounds merged by the whole workgroup
+    cases["m2000_ties"] = np.concatenate([rng.choice(np.array([1, 2, 2, 3, 7], np.uint32), size=2000),
+                                          np.zeros(96, np.uint32)])
+    cases["m3000_geom"] = np.maximum(1, (1e9 * 0.995 ** np.arange(3000))).astype(np.uint32)
     # the sum of counts just below / at 2^32 - 1 (register path / general path)
     h = np.zeros(1024, np.uint32); h[:200] = 1; h[500] = 0xFFFFFFFE - 200 - 7; h[501:508] = 1
     assert int(h.sum(dtype=np.uint64)) == 0xFFFFFFFE
