@@ -209,9 +209,11 @@ size_t hf_batch_workspace_bytes(const hf_stream_desc* descs, uint32_t nstreams);
 
 /*
  * Encodes all streams with one launch per stage, whatever their number:
- * per-slab histograms of every stream; one workgroup per stream that reduces
- * them, builds the stream's book (as hf_build_codebook) and places its
- * slabs; then every slab of every stream is encoded as hf_encode does.
+ * per-slab histograms of every stream; their sum per stream (the stream's
+ * histogram, written to hist when given); one workgroup per stream that
+ * builds its book (as hf_build_codebook); the bit total of every slab; then
+ * every slab of every stream is encoded as hf_encode does (Sec. 4.1-4.3
+ * applied to each stream).
  * `descs` is a HOST array of nstreams descriptors; the plan derived from it
  * is copied to the workspace through library-owned pinned host buffers
  * (reused once their copy has completed) before the kernels run, so descs

@@ -25,13 +25,13 @@ uint32_t log2_exact(uint32_t x) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
-// Slabs of a batched stream: at least 16 blocks (64 Ki symbols), and enough
+// Slabs of a batched stream: at least 32 blocks (128 Ki symbols), and enough
 // symbols that the per-slab counts stay near 1/64 of the stream's bytes.
 uint32_t batch_slabs(uint64_t n, uint32_t sym_bytes, uint32_t alphabet) {
   const uint64_t nblocks = (n + hf::kSlabBlock - 1) / hf::kSlabBlock;
   if (nblocks == 0) return 0;
   uint64_t per = ((uint64_t)alphabet * 4 * 64 / sym_bytes + hf::kSlabBlock - 1) / hf::kSlabBlock;
-  if (per < 16) per = 16;
+  if (per < 32) per = 32;
   uint64_t s = (nblocks + per - 1) / per;
   if (s > nblocks) s = nblocks;
   if (s > hf::kMaxSlabs) s = hf::kMaxSlabs;
@@ -53,10 +53,11 @@ struct Plan {
   std::vector<uint32_t> item_stream;  // stream of every item
   std::vector<uint32_t> hist_items;   // items by histogram group
   std::vector<uint32_t> enc_items;    // items by encoder group
+  std::vector<uint32_t> red_items;    // (stream << 6 | bin chunk) of the histogram reduction
   uint32_t hist_start[kHistGroups] = {}, hist_count[kHistGroups] = {};
   uint32_t enc_start[kEncGroups] = {}, enc_count[kEncGroups] = {};
-  size_t off_streams = 0, off_item_stream = 0, off_hist_items = 0, off_enc_items = 0, header_bytes = 0,
-         total_bytes = 0;
+  size_t off_streams = 0, off_item_stream = 0, off_hist_items = 0, off_enc_items = 0, off_red_items = 0,
+         header_bytes = 0, total_bytes = 0;
 };
 
 hf_status validate(const hf_stream_desc& d) {
@@ -93,7 +94,17 @@ hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t
   o += align256(4 * nitems);
   p.off_enc_items = o;
   o += align256(4 * nitems);
+  uint64_t nred = 0;
+  for (uint32_t s = 0; s < ns; ++s)
+    if (descs[s].n) nred += (descs[s].book.alphabet + hf::kBatchReduceBins - 1) / hf::kBatchReduceBins;
+  p.off_red_items = o;
+  o += align256(4 * nred);
   p.header_bytes = o;
+  p.red_items.clear();
+  p.red_items.reserve(nred);
+  for (uint32_t s = 0; s < ns; ++s)
+    if (descs[s].n)
+      for (uint32_t c = 0; c * hf::kBatchReduceBins < descs[s].book.alphabet; ++c) p.red_items.push_back(s << 6 | c);
   p.bs.resize(ns);
   p.item_stream.clear();
   p.item_stream.reserve(nitems);
@@ -250,6 +261,7 @@ hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* 
     memcpy(sg->host + p.off_item_stream, p.item_stream.data(), 4 * p.item_stream.size());
     memcpy(sg->host + p.off_hist_items, p.hist_items.data(), 4 * p.hist_items.size());
     memcpy(sg->host + p.off_enc_items, p.enc_items.data(), 4 * p.enc_items.size());
+    memcpy(sg->host + p.off_red_items, p.red_items.data(), 4 * p.red_items.size());
     if (hipMemcpyAsync(ws, sg->host, p.header_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return HF_ERR_LAUNCH;
     if (hipEventRecord(sg->done, st) != hipSuccess) return HF_ERR_LAUNCH;
   }
@@ -265,6 +277,9 @@ hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* 
                                    hf::batch_hist_lds_words(hist_alpha[k]), st) != hipSuccess)
       return HF_ERR_LAUNCH;
   }
+  if (hf::launch_batch_hist_reduce(d_streams, (const uint32_t*)(ws + p.off_red_items), (uint32_t)p.red_items.size(),
+                                   st) != hipSuccess)
+    return HF_ERR_LAUNCH;
   if (hf::launch_batch_codebook(d_streams, nstreams, st) != hipSuccess) return HF_ERR_LAUNCH;
   if (hf::launch_batch_slab_bits(d_streams, d_item_stream, nitems, st) != hipSuccess) return HF_ERR_LAUNCH;
   timer.before(st);

@@ -980,23 +980,20 @@ __global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict
   codebook_block<NT>(hist, book, ws, status, lds);
 }
 
-// Batched stage 2: workgroup s sums stream s's per-slab counts into its
-// histogram and builds its book.
+// Batched stage 3: workgroup s builds stream s's book from its histogram
+// (an empty stream's histogram is zeroed here and its one offset set).
 constexpr int kBatchCbThreads = 256;
 
 __global__ __launch_bounds__(kBatchCbThreads) void batch_codebook_kernel(const BatchStream* __restrict__ streams) {
   __shared__ CbLds lds;
   const BatchStream bs = streams[blockIdx.x];
   const uint32_t tid = threadIdx.x;
-  const uint32_t A = bs.A;
-  if (bs.n == 0 && tid == 0) bs.offsets[0] = 0;
-  for (uint32_t b = tid; b < A; b += kBatchCbThreads) {
-    uint32_t c = 0;
-    for (uint32_t g = 0; g < bs.nslabs; ++g) c += bs.part[(uint64_t)g * A + b];
-    bs.hist[b] = c;
+  if (bs.n == 0) {
+    for (uint32_t b = tid; b < bs.A; b += kBatchCbThreads) bs.hist[b] = 0;
+    if (tid == 0) bs.offsets[0] = 0;
+    __threadfence_block();
+    __syncthreads();
   }
-  __threadfence_block();
-  __syncthreads();
   codebook_block<kBatchCbThreads>(bs.hist, bs.book, bs.cb_ws, bs.status, lds);
 }
 

@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G);
 }
 
-// Batched stage 3: bit total and last 32 content bits of slab g of stream s
+// Batched stage 4: bit total and last 32 content bits of slab g of stream s
 // for work item i = streams[s].item0 + g, from the slab's counts.
 __global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const BatchStream* __restrict__ streams,
                                                                       const uint32_t* __restrict__ item_stream) {
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const Batc
   }
 }
 
-// Batched stage 4: workgroup i encodes slab g of stream s for work item
+// Batched stage 5: workgroup i encodes slab g of stream s for work item
 // items[i] = streams[s].item0 + g; its first bit is the sum of the bit
 // totals of the stream's earlier slabs.  Each stream has its own alphabet,
 // symbol width and codebook.

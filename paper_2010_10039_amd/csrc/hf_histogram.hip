@@ -243,7 +243,32 @@ __global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const Bat
   if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
 }
 
-uint32_t batch_hist_lds_words(uint32_t max_alphabet) { return std::max<uint32_t>(4096u, max_alphabet) + 16u; }
+// Batched stage 2: workgroup i sums, for stream s = item >> 6 and bins
+// [256 c, 256 c + 256) with c = item & 63, the counts of every slab of s
+// into its histogram (coalesced row segments, one store per bin).
+__global__ __launch_bounds__(kBatchReduceBins) void batch_hist_reduce_kernel(const BatchStream* __restrict__ streams,
+                                                                             const uint32_t* __restrict__ items) {
+  const uint32_t item = items[blockIdx.x];
+  const BatchStream& bs = streams[item >> 6];
+  const uint32_t b = (item & 63) * kBatchReduceBins + threadIdx.x;
+  if (b >= bs.A) return;
+  const uint32_t* p = bs.part + b;
+  uint32_t c = 0;
+#pragma unroll 8
+  for (uint32_t g = 0; g < bs.nslabs; ++g) c += p[(uint64_t)g * bs.A];
+  bs.hist[b] = c;
+}
+
+hipError_t launch_batch_hist_reduce(const BatchStream* d_streams, const uint32_t* d_red_items, uint32_t nred,
+                                    hipStream_t stream) {
+  if (nred == 0) return hipSuccess;
+  batch_hist_reduce_kernel<<<nred, kBatchReduceBins, 0, stream>>>(d_streams, d_red_items);
+  return hipGetLastError();
+}
+
+// Two replicas of the largest alphabet (more for smaller ones): peaked
+// streams put many lanes on one bin, and every replica splits them.
+uint32_t batch_hist_lds_words(uint32_t max_alphabet) { return std::max<uint32_t>(4096u, 2 * max_alphabet) + 16u; }
 
 hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                   const uint32_t* d_items, uint32_t nitems, uint32_t lds_words,

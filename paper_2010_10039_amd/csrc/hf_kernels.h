@@ -105,6 +105,11 @@ uint32_t batch_hist_lds_words(uint32_t max_alphabet);
 hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                   const uint32_t* d_items, uint32_t nitems, uint32_t lds_words,
                                   hipStream_t stream);
+// Bins one workgroup of the batched histogram reduction sums (alphabets up
+// to 8192 give at most 32 chunks, encoded in 6 bits of a reduce item).
+constexpr uint32_t kBatchReduceBins = 256;
+hipError_t launch_batch_hist_reduce(const BatchStream* d_streams, const uint32_t* d_red_items, uint32_t nred,
+                                    hipStream_t stream);
 hipError_t launch_batch_codebook(const BatchStream* d_streams, uint32_t nstreams, hipStream_t stream);
 hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
                                   hipStream_t stream);
