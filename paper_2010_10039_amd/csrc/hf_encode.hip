@@ -209,9 +209,13 @@ struct EncShared {
   uint32_t tailw;    // wide mode: current tile's last 32 bits
 };
 
+// `expect` is the slab's bit total from the prepass (sum of count * cl): a
+// table-mode slab whose tiles add up to anything else held a symbol without
+// code or outside the alphabet.
 template <int R, int SB, int MODE>
 __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* tab, uint32_t* buf,
-                                            uint32_t* dummy, EncShared& sh, uint32_t g, uint64_t G) {
+                                            uint32_t* dummy, EncShared& sh, uint32_t g, uint64_t G,
+                                            uint64_t expect) {
   constexpr uint32_t NS = 1u << R;
   constexpr uint32_t T = kEncThreads * NS;
   const uint32_t tid = threadIdx.x;
@@ -237,16 +241,16 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     if (MODE == kModeTable && s_lo + (uint64_t)(t + 1) * T <= s_hi) {
       // whole tile inside the slab: no per-symbol branches; tab[A] = 0 catches
       // symbols outside the alphabet, a zero entry marks a symbol without code
-      uint32_t mn = 0xFFFFFFFFu, fsum = 0;
+      // (a zero entry counts 32 bits here; the slab's total then differs
+      // from the prepass's, which flags it at the end of the slab)
+      uint32_t fsum = 0;
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i) {
         const uint32_t e = tab[min(raw.symbol(i), a.A)];
         ent[i] = e;
         fsum += e & 31;
-        mn = min(mn, e);
       }
       L = 32 * NS - fsum;
-      bad = mn == 0;
       full_tile = true;
     } else {
 #pragma unroll
@@ -366,17 +370,11 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     const uint32_t nw = (uint32_t)(wend - w0);
     const uint32_t pred = sh.tail[t & 1];
     if (MODE != kModeWide) {
-      for (uint32_t i = tid; i < nw; i += kEncThreads) {
-        uint32_t v;
-        if (q == 0) {
-          v = buf[i];
-        } else {
-          const uint32_t hi = i == 0 ? pred : buf[i - 1];
-          v = (hi << (32 - q)) | (buf[i] >> q);
-        }
-        const uint64_t wi = w0 + i;
-        if (wi < a.cap_words) a.out[wi] = v;
-      }
+      // word i is bits [32 i - q, 32 i - q + 32) of the tile: buf[-1] holds
+      // the previous tile's last 32 bits, and alignbit(hi, lo, 0) is lo
+      const uint32_t nwc = w0 >= a.cap_words ? 0u : (uint32_t)min((uint64_t)nw, a.cap_words - w0);
+      uint32_t* const dst = a.out + w0;
+      for (uint32_t i = tid; i < nwc; i += kEncThreads) dst[i] = __builtin_amdgcn_alignbit(buf[i - 1], buf[i], q);
     } else {
       for (uint32_t i = tid; i < nw; i += kEncThreads) {
         const uint64_t wi = w0 + i;
@@ -410,13 +408,16 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     run += B;
     __syncthreads();
     if (MODE != kModeWide) {
-      // clear what this tile used (one word past the content is read above)
+      // clear what this tile used (one word past the content is read above);
+      // the next tile's gather finds this tile's last 32 bits in buf[-1]
       const uint32_t used = (B + 31) / 32 + 1;
       for (uint32_t i = tid; i < used; i += kEncThreads) buf[i] = 0;
+      if (tid == 0) buf[-1] = sh.tail[(t + 1) & 1];
     } else if (tid == 0) {
       sh.tailw = 0;
     }
   }
+  if (MODE == kModeTable && tid == 0 && run != expect) raise_status(a.status, HF_ERR_SYMBOL);
 }
 
 template <int R, int SB>
@@ -429,9 +430,10 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   const uint32_t lmax = (uint32_t)a.info[1];
   const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
   const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  // LDS: [tile buffer: T + 2 words][table: A + 1 entries, if A <= 8192][kEncThreads dummy words]
-  uint32_t* buf = lds;
-  uint32_t* tab = lds + T + 2;
+  // LDS: [previous tile's last word][tile buffer: T + 2 words][table: A + 1
+  // entries, if A <= 8192][kEncThreads dummy words]
+  uint32_t* buf = lds + 1;
+  uint32_t* tab = lds + T + 3;
   uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
@@ -447,15 +449,16 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   if (lane_id() == 0) sh.red[tid / kWave] = G;
   if (tid == 0) {
     sh.tail[0] = g > 0 ? a.tails[g - 1] : 0u;
+    buf[-1] = sh.tail[0];
     sh.tailw = 0;
   }
   __syncthreads();
   G = 0;
 #pragma unroll
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
-  if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, dummy, sh, g, G);
-  else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
-  else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G);
+  if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
+  else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
+  else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
 }
 
 // Batched stage 4: bit total and last 32 content bits of slab g of stream s
@@ -525,8 +528,8 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   const uint32_t lmax = (uint32_t)a.info[1];
   const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
   const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  uint32_t* buf = lds;
-  uint32_t* tab = lds + T + 2;
+  uint32_t* buf = lds + 1;  // same layout as encode_kernel
+  uint32_t* tab = lds + T + 3;
   uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
@@ -541,6 +544,7 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   if (lane_id() == 0) sh.red[tid / kWave] = G;
   if (tid == 0) {
     sh.tail[0] = g > 0 ? bs.slab_tail[g - 1] : 0u;
+    buf[-1] = sh.tail[0];
     sh.tailw = 0;
   }
   __syncthreads();
@@ -548,13 +552,13 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
 #pragma unroll
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
   if (bs.sym_bytes == 1) {
-    if (mode == kModeTable) encode_slab<R, 1, kModeTable>(a, tab, buf, dummy, sh, g, G);
-    else if (mode == kModeGlobal) encode_slab<R, 1, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
-    else encode_slab<R, 1, kModeWide>(a, tab, buf, dummy, sh, g, G);
+    if (mode == kModeTable) encode_slab<R, 1, kModeTable>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else if (mode == kModeGlobal) encode_slab<R, 1, kModeGlobal>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else encode_slab<R, 1, kModeWide>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
   } else {
-    if (mode == kModeTable) encode_slab<R, 2, kModeTable>(a, tab, buf, dummy, sh, g, G);
-    else if (mode == kModeGlobal) encode_slab<R, 2, kModeGlobal>(a, tab, buf, dummy, sh, g, G);
-    else encode_slab<R, 2, kModeWide>(a, tab, buf, dummy, sh, g, G);
+    if (mode == kModeTable) encode_slab<R, 2, kModeTable>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else if (mode == kModeGlobal) encode_slab<R, 2, kModeGlobal>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else encode_slab<R, 2, kModeWide>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
   }
 }
 
@@ -580,7 +584,7 @@ EncodeFn pick(uint32_t r, uint32_t sb) {
 
 size_t encode_lds_bytes(uint32_t A, uint32_t r) {
   const size_t T = (size_t)kEncThreads << r;
-  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 2);
+  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 3);
 }
 
 // Resident workgroups per CU, cached per kernel and LDS size.
@@ -690,7 +694,7 @@ hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_i
                                hipStream_t stream) {
   if (nitems == 0) return hipSuccess;
   const size_t T = (size_t)kEncThreads << r;
-  const size_t lds = 4 * (T + 2 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
+  const size_t lds = 4 * (T + 3 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
   using Fn = void (*)(const BatchStream*, const uint32_t*, const uint32_t*);
   Fn fn;
   switch (r) {
