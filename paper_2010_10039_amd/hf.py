@@ -99,8 +99,16 @@ def _stream() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _dptr(t: torch.Tensor) -> int:
+    """Device address of a GPU tensor; host tensors are refused here, since
+    the kernels would dereference their addresses on the device."""
+    if not t.is_cuda:
+        raise ValueError(f"libhf takes GPU tensors only, got a {t.device} tensor of shape {tuple(t.shape)}")
+    return t.data_ptr()
+
+
 def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
-    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+    return ctypes.c_void_p(0 if t is None else _dptr(t))
 
 
 def _sym_bytes(sym: torch.Tensor) -> int:
@@ -180,8 +188,8 @@ class Codebook:
         )
 
     def struct(self) -> hf_codebook:
-        return hf_codebook(self.alphabet, self.cl.data_ptr(), self.cw.data_ptr(), self.first.data_ptr(),
-                           self.entry.data_ptr(), self.rev.data_ptr(), self.info.data_ptr())
+        return hf_codebook(self.alphabet, _dptr(self.cl), _dptr(self.cw), _dptr(self.first), _dptr(self.entry),
+                           _dptr(self.rev), _dptr(self.info))
 
 
 def hf_histogram(sym: torch.Tensor, alphabet: int, hist: torch.Tensor | None = None,
@@ -353,17 +361,17 @@ class BatchEncoder:
             self.outs.append(out)
             self.offsets.append(offs)
             d = self.descs[i]
-            d.sym = x.data_ptr() if x.numel() else 0
+            d.sym = _dptr(x) if x.numel() else 0
             d.n = x.numel()
             d.sym_bytes = sb
             d.chunk_symbols = chunks[i]
             d.reduce_log2 = rs[i]
             d.reserved = 0
-            d.hist = hist.data_ptr()
+            d.hist = _dptr(hist)
             d.book = book.struct()
-            d.out = out.data_ptr()
+            d.out = _dptr(out)
             d.out_capacity_words = out.numel()
-            d.chunk_bit_offsets = offs.data_ptr()
+            d.chunk_bit_offsets = _dptr(offs)
         nbytes = hf_batch_workspace_bytes(self.descs)
         if nbytes == 0:
             raise HFError(HF_ERR_ARG, "BatchEncoder")

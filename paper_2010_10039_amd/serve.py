@@ -412,12 +412,12 @@ class GpuExecutor:
                 descs = (hf.hf_stream_desc * len(small))()
                 for k, r in enumerate(small):
                     d, res = descs[k], r.result
-                    d.sym, d.n, d.sym_bytes = (r.sym.data_ptr() if r.n else 0), r.n, r.sym_bytes
+                    d.sym, d.n, d.sym_bytes = (hf._dptr(r.sym) if r.n else 0), r.n, r.sym_bytes
                     d.chunk_symbols, d.reduce_log2, d.reserved = r.chunk, r.r, 0
-                    d.hist = res.hist.data_ptr()
+                    d.hist = hf._dptr(res.hist)
                     d.book = res.book.struct()
-                    d.out, d.out_capacity_words = res.out.data_ptr(), res.out.numel()
-                    d.chunk_bit_offsets = res.offsets.data_ptr()
+                    d.out, d.out_capacity_words = hf._dptr(res.out), res.out.numel()
+                    d.chunk_bit_offsets = hf._dptr(res.offsets)
                 ws = cws.take(batch.ws[1] - ALIGN, torch.uint8)
                 hf.hf_encode_batch(descs, ws, status[:len(small)])
             for k, r in enumerate(large):

@@ -180,6 +180,12 @@ def zipf_codes(n: int, alphabet: int, s: float, generator, device="cpu"):
     return perm[idx]
 
 
+def poisson_arrivals(nreq: int, qps: float, seed: int = 7) -> list:
+    """Arrival times (seconds) of a Poisson process of rate qps."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / qps, size=nreq)).tolist()
+
+
 def served_requests(nreq: int = 200, seed: int = 2000, qps: float = 2000.0, min_bytes: float = 2.0 ** 20,
                     max_bytes: float = 2.0 ** 29, device: str = "cpu"):
     """A trace of compression requests (the served workload).

@@ -134,3 +134,17 @@ def test_batch_descriptor_checks(lib):
         arr = (hf.hf_stream_desc * 2)(desc(), desc(**kw))
         assert f(arr, 2) == 0, kw
         assert g(arr, 2, ctypes.c_void_p(0x10000), 1 << 20, ctypes.c_void_p(0x20000), None) == 1, kw
+
+
+def test_binding_refuses_host_tensors():
+    """The Python binding passes device addresses only: a host tensor is
+    refused before any library call (its address would be dereferenced by a
+    kernel)."""
+    torch = pytest.importorskip("torch")
+    from paper_2010_10039_amd import hf
+
+    x = torch.zeros(1000, dtype=torch.int16)
+    with pytest.raises(ValueError, match="GPU tensors only"):
+        hf._dptr(x)
+    with pytest.raises(ValueError, match="GPU tensors only"):
+        hf.hf_histogram(x, 1024, status=torch.zeros(1, dtype=torch.int32))
