@@ -636,41 +636,41 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
 
   // ---- 1. compaction ---------------------------------------------------------
   compact<NT>(hist, book.alphabet, key, usym, book, L.sh.wtot);
+  uint32_t* rk = (uint32_t*)L.mw + 1024;  // [kSmallUsed] rank of each key
   for (uint32_t i = tid; i < kSmallUsed; i += NT) iw[i] = 0;
+  for (uint32_t i = tid; i < kSmallUsed; i += NT) {
+    rk[i] = 0;
+    if (i >= m) key[i] = ~0ull;  // above every used key
+  }
   for (uint32_t l = tid; l <= kMaxLen; l += NT) L.sh.cnt[l] = 0;
   __syncthreads();
 
-  // ---- 2. rank sort: wave w ranks keys [64w, 64w + 64) against all keys -------
-  // Keys are in compact-index order, so the rank of e by (weight, index) is
-  // #{j < e: w_j <= w_e} + #{j > e: w_j < w_e}, all on 32-bit weights.
-  if (wave < kSmallUsed / kWave) {
-    const uint32_t e = wave * kWave + lane;
-    const uint32_t we = e < m ? (uint32_t)(key[e] >> 16) : kInf32;
-    uint32_t W[kSmallUsed / kWave];
+  // ---- 2. rank sort: rank(e) = #{j : key_j < key_e} ---------------------------
+  // key = count << 16 | u with u the compact (symbol-order) index, so this
+  // is the rank by (count, symbol).  Each of the 16 (block of e, block of j)
+  // pairs of 64-key blocks is counted by one wave from broadcast LDS reads;
+  // the partial ranks meet in LDS.
+  {
+    const uint32_t nb = (m + kWave - 1) / kWave;
+    for (uint32_t p = wave; p < 16; p += NT / kWave) {
+      const uint32_t eb = p & 3, jb = p >> 2;
+      if (eb >= nb || jb >= nb) continue;
+      const uint32_t e = eb * kWave + lane;
+      const uint64_t ke = key[e];
+      const uint64_t* kj = key + jb * kWave;
+      uint32_t c[4] = {0, 0, 0, 0};
+      for (uint32_t j0 = 0; j0 < (uint32_t)kWave; j0 += 16) {
 #pragma unroll
-    for (uint32_t r = 0; r < kSmallUsed / kWave; ++r)
-      W[r] = r * kWave + lane < m ? (uint32_t)(key[r * kWave + lane] >> 16) : kInf32;
-    uint32_t acc[4] = {0, 0, 0, 0};
-    for (uint32_t r = 0; r < kSmallUsed / kWave && r * kWave < m; ++r) {
-      uint32_t Wr = W[0];
-#pragma unroll
-      for (uint32_t q = 1; q < kSmallUsed / kWave; ++q) Wr = r == q ? W[q] : Wr;
-      if (r < wave) {
-#pragma unroll
-        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) <= we;
-      } else if (r > wave) {
-#pragma unroll
-        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) < we;
-      } else {
-#pragma unroll
-        for (uint32_t l = 0; l < (uint32_t)kWave; ++l) acc[l & 3] += readlane32(Wr, l) < we + (lane > l ? 1u : 0u);
+        for (uint32_t j = 0; j < 16; ++j) c[j & 3] += kj[j0 + j] < ke ? 1u : 0u;
       }
+      if (e < m) atomicAdd(&rk[e], c[0] + c[1] + c[2] + c[3]);
     }
-    const uint32_t rank = acc[0] + acc[1] + acc[2] + acc[3];
-    if (e < m) {
-      lw[rank] = we;
-      lu[rank] = (uint16_t)e;
-    }
+  }
+  __syncthreads();
+  if (tid < m) {
+    const uint32_t r = rk[tid];
+    lw[r] = (uint32_t)(key[tid] >> 16);
+    lu[r] = (uint16_t)tid;
   }
   __syncthreads();
   if (wave != 0) return;
@@ -711,19 +711,28 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
       const uint32_t total = a + b, pairs = total >> 1;
       uint32_t last_leaf, last_int;
       if (a <= (uint32_t)kWave && b <= (uint32_t)kWave) {
-        // internals lighter than my leaf (RI is INF past b), leaves of the
-        // run no heavier than my node (RLa is INF past a); 8 at a time
-        const uint32_t RLa = lane < a ? RL : kInf32;
-        uint32_t c[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
-        for (uint32_t q0 = 0; q0 < b; q0 += 8) {
-#pragma unroll
-          for (uint32_t j = 0; j < 8; ++j) c[j & 3] += readlane32(RI, q0 + j) < RL;
+        // A leaf follows the internal nodes lighter than it, an internal node
+        // the leaves of the run no heavier than it.  Both runs are sorted, so
+        // a loop over the shorter run suffices: one ballot gives how many of
+        // the other run precede each of its elements, and each element of the
+        // other run counts the short-run elements it follows.
+        uint32_t pl = lane, pi = lane;
+        if (b <= a) {
+          const uint64_t amask = a >= (uint32_t)kWave ? ~0ull : (1ull << a) - 1;  // RL past a is not INF
+          for (uint32_t q = 0; q < b; ++q) {
+            const uint32_t wq = readlane32(RI, q);
+            const uint32_t k = (uint32_t)__popcll(__ballot(RL <= wq) & amask);  // leaves [0, k) precede q
+            pl += lane >= k ? 1u : 0u;
+            pi += lane == q ? k : 0u;
+          }
+        } else {
+          for (uint32_t j = 0; j < a; ++j) {
+            const uint32_t wj = readlane32(RL, j);
+            const uint32_t k = (uint32_t)__popcll(__ballot(RI < wj));  // internals [0, k) precede j (RI is INF past b)
+            pi += lane >= k ? 1u : 0u;
+            pl += lane == j ? k : 0u;
+          }
         }
-        for (uint32_t j0 = 0; j0 < a; j0 += 8) {
-#pragma unroll
-          for (uint32_t j = 0; j < 8; ++j) d[j & 3] += readlane32(RLa, j0 + j) <= RI;
-        }
-        const uint32_t pl = lane + c[0] + c[1] + c[2] + c[3], pi = lane + d[0] + d[1] + d[2] + d[3];
         if (lane < a && pl < 2 * pairs) {
           parl[lc + lane] = (uint16_t)(it + (pl >> 1));
           atomicAdd(&iw[it + (pl >> 1)], RL);
@@ -882,27 +891,32 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   wave_sync();
 
   // ---- 5c. codewords: rank within each length in symbol order -------------------
-  uint32_t next = below;  // lane l-1: next rev slot of length l
+  // The lanes of a 64-symbol chunk that share my length are the AND over
+  // the length's 7 bits of that bit's ballot or its complement (unused
+  // lanes carry length 0, which no used symbol has).  The last lane of each
+  // length advances that length's next rev slot.
+  uint32_t* ns = (uint32_t*)L.mw + 2048;  // [kMaxLen + 1] next rev slot per length
+  ns[len] = below;
+  wave_sync();
   for (uint32_t u0 = 0; u0 < m; u0 += kWave) {
     const uint32_t u = u0 + lane;
     const bool valid = u < m;
     const uint32_t l = valid ? L.clu[u] : 0u;
-    uint32_t pos = 0;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lv = readlane32(l, (uint32_t)leader);
-      const uint64_t mask = __ballot(valid && l == lv);
-      const uint32_t slot0 = readlane32(next, lv - 1);
-      if (valid && l == lv) pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
-      if (lane == lv - 1) next += (uint32_t)__popcll(mask);
-      pending &= ~mask;
+    uint64_t eq = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < 7; ++bit) {
+      const bool on = (l >> bit) & 1u;
+      const uint64_t B = __ballot(on);
+      eq &= on ? B : ~B;
     }
     if (valid) {
+      const uint32_t pos = ns[l] + (uint32_t)__popcll(eq & lanemask_lt());
       const uint32_t s = usym[u];
       book.rev[pos] = s;
       book.cw[s] = fl[l] + (pos - el[l]);
+      if ((eq >> lane) == 1ull) ns[l] = pos + 1;
     }
+    wave_sync();
   }
 }
 
