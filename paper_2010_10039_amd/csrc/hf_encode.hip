@@ -227,11 +227,20 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
   Raw<NS, SB> raw;
   raw.load(a.sym, s_lo + (uint64_t)tid * NS, s_hi, a.vec_ok != 0);
   uint64_t run = 0;  // bits of this slab before the current tile
+  // buf word i is output word (tile's first bit) / 32 + i: the first word
+  // starts with the last (first bit % 32) bits before the tile, seeded here
+  // for the slab's first tile and carried over for the others
+  if (MODE != kModeWide && tid == 0) {
+    const uint32_t q0 = (uint32_t)(G & 31);
+    buf[0] = q0 ? sh.tail[0] << (32 - q0) : 0u;
+  }
 
   for (uint32_t t = 0; t < ntiles; ++t) {
     const uint64_t s0 = s_lo + (uint64_t)t * T + (uint64_t)tid * NS;
     const uint32_t nvalid = s0 >= s_hi ? 0u : (s_hi - s0 >= NS ? NS : (uint32_t)(s_hi - s0));
     const bool last_tile = t == ntiles - 1;
+    const uint64_t Gt = G + run;            // the tile's first bit in the stream
+    const uint32_t q = (uint32_t)(Gt & 31);  // ... and its offset in buf[0]
 
     // ---- lookup: packed entries (table mode) or symbols; lane bit count ----
     uint32_t ent[NS];
@@ -294,8 +303,8 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       // completes per code (<= 27 bits on <= 31 pending); the OR always
       // issues, into this lane's dummy word when none does.
       uint32_t pend = 0;
-      uint32_t nb = P & 31;
-      uint32_t* wp = buf + (P >> 5);
+      uint32_t nb = (P + q) & 31;
+      uint32_t* wp = buf + ((P + q) >> 5);
       uint32_t* const sink = dummy + tid;
       if (full_tile) {
 #pragma unroll
@@ -325,8 +334,8 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       if (nb) atomicOr(wp, pend << (32 - nb));
     } else if (MODE == kModeGlobal) {
       uint64_t acc = 0;
-      uint32_t nb = P & 31;
-      uint64_t wi = P >> 5;
+      uint32_t nb = (P + q) & 31;
+      uint64_t wi = (P + q) >> 5;
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i)
         if (ent[i] != 0xFFFFFFFFu) push_bits(acc, nb, wi, buf, ~0ull, (uint32_t)a.cw[ent[i]], a.cl[ent[i]]);
@@ -345,37 +354,33 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     }
     __syncthreads();
 
-    // ---- this tile's last 32 bits, for the next tile of the slab -------------------
-    if (tid == 0) {
-      uint32_t tail;
-      if (MODE == kModeWide) {
-        tail = sh.tailw;
-      } else if (B >= 32) {
-        const uint32_t o = B & 31, w = (B >> 5) - 1;
-        tail = o ? ((buf[w] << o) | (buf[w + 1] >> (32 - o))) : buf[w];
-      } else {
-        tail = B ? (buf[0] >> (32 - B)) : 0u;
-      }
-      sh.tail[(t + 1) & 1] = tail;
-    }
+    // ---- wide mode: this tile's last 32 bits, for the next tile of the slab ----------
+    if (MODE == kModeWide && tid == 0) sh.tail[(t + 1) & 1] = sh.tailw;
 
     // ---- gathering ----------------------------------------------------------------
-    const uint64_t Gt = G + run;
-    const uint32_t q = (uint32_t)(Gt & 31);
+    const uint32_t q_end = q + B;  // bit after the tile's last, counted from buf[0]
     const uint64_t w0 = Gt >> 5;
     const uint64_t end_bit = Gt + B;
     const bool stream_end = last_slab && last_tile;
     uint64_t wend = (end_bit + 31) >> 5;
     if (!stream_end && (end_bit & 31)) wend -= 1;  // the next tile owns the shared word
     const uint32_t nw = (uint32_t)(wend - w0);
-    const uint32_t pred = sh.tail[t & 1];
+    uint32_t carry = 0;  // the shared word's bits so far, for the next tile's buf[0]
     if (MODE != kModeWide) {
-      // word i is bits [32 i - q, 32 i - q + 32) of the tile: buf[-1] holds
-      // the previous tile's last 32 bits, and alignbit(hi, lo, 0) is lo
+      // buf holds the output words w0 .. w0 + nw - 1 as they are: copy them,
+      // four per lane from one 16-byte LDS read
       const uint32_t nwc = w0 >= a.cap_words ? 0u : (uint32_t)min((uint64_t)nw, a.cap_words - w0);
       uint32_t* const dst = a.out + w0;
-      for (uint32_t i = tid; i < nwc; i += kEncThreads) dst[i] = __builtin_amdgcn_alignbit(buf[i - 1], buf[i], q);
+      for (uint32_t i = 4 * tid; i < nwc; i += 4 * kEncThreads) {
+        const uint4 v = *(const uint4*)(buf + i);
+        dst[i] = v.x;
+        if (i + 1 < nwc) dst[i + 1] = v.y;
+        if (i + 2 < nwc) dst[i + 2] = v.z;
+        if (i + 3 < nwc) dst[i + 3] = v.w;
+      }
+      if (tid == 0 && (q_end & 31)) carry = buf[q_end >> 5];
     } else {
+      const uint32_t pred = sh.tail[t & 1];
       for (uint32_t i = tid; i < nw; i += kEncThreads) {
         const uint64_t wi = w0 + i;
         if (wi < a.cap_words) a.out[wi] = (i == 0 && q) ? (pred << (32 - q)) : 0u;
@@ -408,11 +413,10 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     run += B;
     __syncthreads();
     if (MODE != kModeWide) {
-      // clear what this tile used (one word past the content is read above);
-      // the next tile's gather finds this tile's last 32 bits in buf[-1]
-      const uint32_t used = (B + 31) / 32 + 1;
-      for (uint32_t i = tid; i < used; i += kEncThreads) buf[i] = 0;
-      if (tid == 0) buf[-1] = sh.tail[(t + 1) & 1];
+      // clear the words this tile used; the shared word's bits start the next
+      const uint32_t used = (q_end >> 5) + 1;
+      for (uint32_t i = 4 * tid; i < used; i += 4 * kEncThreads) *(uint4*)(buf + i) = make_uint4(0u, 0u, 0u, 0u);
+      if (tid == 0) buf[0] = carry;
     } else if (tid == 0) {
       sh.tailw = 0;
     }
@@ -423,17 +427,17 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
 template <int R, int SB>
 __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   constexpr uint32_t T = kEncThreads << R;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared sh;
   const uint32_t tid = threadIdx.x;
   const uint32_t g = blockIdx.x;
   const uint32_t lmax = (uint32_t)a.info[1];
   const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
   const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  // LDS: [previous tile's last word][tile buffer: T + 2 words][table: A + 1
-  // entries, if A <= 8192][kEncThreads dummy words]
-  uint32_t* buf = lds + 1;
-  uint32_t* tab = lds + T + 3;
+  // LDS: [tile buffer: T + 8 words, 16-byte aligned][table: A + 1 entries,
+  // if A <= 8192][kEncThreads dummy words]
+  uint32_t* buf = lds;
+  uint32_t* tab = lds + T + 8;
   uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
       tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
     }
   if (mode != kModeWide)
-    for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
+    for (uint32_t i = tid; i < T + 8; i += kEncThreads) buf[i] = 0;
   // this slab's first bit: the bit totals of all earlier slabs
   uint64_t G = 0;
   for (uint32_t k = tid; k < g; k += kEncThreads) G += a.bits[k];
@@ -449,7 +453,6 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   if (lane_id() == 0) sh.red[tid / kWave] = G;
   if (tid == 0) {
     sh.tail[0] = g > 0 ? a.tails[g - 1] : 0u;
-    buf[-1] = sh.tail[0];
     sh.tailw = 0;
   }
   __syncthreads();
@@ -501,7 +504,7 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
                                                                    const uint32_t* __restrict__ item_stream,
                                                                    const uint32_t* __restrict__ items) {
   constexpr uint32_t T = kEncThreads << R;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared sh;
   const uint32_t tid = threadIdx.x;
   const uint32_t item = items[blockIdx.x];
@@ -528,8 +531,8 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   const uint32_t lmax = (uint32_t)a.info[1];
   const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
   const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  uint32_t* buf = lds + 1;  // same layout as encode_kernel
-  uint32_t* tab = lds + T + 3;
+  uint32_t* buf = lds;  // same layout as encode_kernel
+  uint32_t* tab = lds + T + 8;
   uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
   if (mode == kModeTable)
     for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
@@ -537,14 +540,13 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
       tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
     }
   if (mode != kModeWide)
-    for (uint32_t i = tid; i < T + 2; i += kEncThreads) buf[i] = 0;
+    for (uint32_t i = tid; i < T + 8; i += kEncThreads) buf[i] = 0;
   uint64_t G = 0;
   for (uint32_t k = tid; k < g; k += kEncThreads) G += bs.slab_bits[k];
   G = wave_sum_u64(G);
   if (lane_id() == 0) sh.red[tid / kWave] = G;
   if (tid == 0) {
     sh.tail[0] = g > 0 ? bs.slab_tail[g - 1] : 0u;
-    buf[-1] = sh.tail[0];
     sh.tailw = 0;
   }
   __syncthreads();
@@ -584,7 +586,7 @@ EncodeFn pick(uint32_t r, uint32_t sb) {
 
 size_t encode_lds_bytes(uint32_t A, uint32_t r) {
   const size_t T = (size_t)kEncThreads << r;
-  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 3);
+  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 8);
 }
 
 // Resident workgroups per CU, cached per kernel and LDS size.
@@ -690,7 +692,7 @@ hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_i
                                hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
   if (nitems == 0) return hipSuccess;
   const size_t T = (size_t)kEncThreads << r;
-  const size_t lds = 4 * (T + 3 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
+  const size_t lds = 4 * (T + 8 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
   using Fn = void (*)(const BatchStream*, const uint32_t*, const uint32_t*);
   Fn fn;
   switch (r) {
