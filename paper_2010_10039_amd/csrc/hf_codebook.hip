@@ -99,7 +99,6 @@ constexpr uint32_t kOneWaveRoundsMax = 1024;
 struct Shared {
   uint64_t wsum[kCbMaxWaves];
   uint32_t wmax[kCbMaxWaves];
-  uint32_t rcnt[kCbMaxWaves * 16];  // radix sort: digit counts, then offsets, per wave
   uint32_t wtot[kCbMaxWaves];
   uint32_t cnt[kMaxLen + 1];
   uint32_t cntw[kCbMaxWaves][kMaxLen + 1];
@@ -108,19 +107,25 @@ struct Shared {
   uint64_t total;
   uint32_t a;
   uint32_t lmax, lmin;
+  uint32_t rend[256];  // workgroup rounds: internal nodes created up to the end of each round
 };
 
-// Per-wave aggregation of equal values before one LDS atomic per distinct
-// value: lanes with the same code length add their count in one go.
+constexpr uint32_t kRoundEndsMax = 256;
+
+// Per-wave aggregation of equal lengths before one LDS atomic per distinct
+// length: the lanes sharing my length are the AND over the length's 7 bits
+// of that bit's ballot or its complement, and the last of them adds their
+// number.
 __device__ __forceinline__ void count_lengths(uint32_t l, bool valid, uint32_t* cnt) {
-  uint64_t pending = __ballot(valid);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
-    const uint64_t mask = __ballot(valid && l == lv);
-    if (lane_id() == leader) atomicAdd(&cnt[lv], (uint32_t)__popcll(mask));
-    pending &= ~mask;
+  const uint32_t lv = valid ? l : 0u;  // used symbols have lengths >= 1
+  uint64_t eq = ~0ull;
+#pragma unroll
+  for (int bit = 0; bit < 7; ++bit) {
+    const bool on = (lv >> bit) & 1u;
+    const uint64_t B = __ballot(on);
+    eq &= on ? B : ~B;
   }
+  if (valid && (eq >> lane_id()) == 1ull) atomicAdd(&cnt[lv], (uint32_t)__popcll(eq));
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
@@ -239,19 +244,29 @@ __device__ __forceinline__ void rounds_one_wave(const Tree<IdT>& t, uint32_t m, 
 template <int NT, typename IdT>
 __device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint32_t A, uint64_t* key, IdT* usym,
                                         const hf_codebook& book, uint32_t* wtot) {
+  constexpr uint32_t V = 4;  // consecutive symbols per lane and chunk
   uint32_t run = 0;
-  for (uint32_t c0 = 0; c0 < A; c0 += NT) {
-    const uint32_t s = c0 + threadIdx.x;
-    const uint32_t h = s < A ? hist[s] : 0u;
+  for (uint32_t c0 = 0; c0 < A; c0 += V * NT) {
+    const uint32_t s = c0 + V * threadIdx.x;
+    uint32_t h[V];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t v = 0; v < V; ++v) {
+      h[v] = s + v < A ? hist[s + v] : 0u;
+      c += h[v] != 0;
+    }
     uint32_t tot;
-    const uint32_t pre = block_exclusive_scan<NT / kWave>(h != 0, wtot, &tot);
-    if (h) {
-      const uint32_t u = run + pre;
-      key[u] = ((uint64_t)h << 16) | u;
-      usym[u] = (IdT)s;
-    } else if (s < A) {
-      book.cl[s] = 0;
-      book.cw[s] = 0;
+    uint32_t u = run + block_exclusive_scan<NT / kWave>(c, wtot, &tot);
+#pragma unroll
+    for (uint32_t v = 0; v < V; ++v) {
+      if (h[v]) {
+        key[u] = ((uint64_t)h[v] << 16) | u;
+        usym[u] = (IdT)(s + v);
+        ++u;
+      } else if (s + v < A) {
+        book.cl[s + v] = 0;
+        book.cw[s + v] = 0;
+      }
     }
     run += tot;
     __syncthreads();  // wtot is reused by the next chunk
@@ -259,54 +274,83 @@ __device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint3
 }
 
 // Stable LSD radix sort of key[0, m) (count << 16 | u, in u order) by the
-// 32-bit count, 4 bits a pass, as many passes as the largest count needs;
-// tmp[0, m) is the other buffer.  Wave w owns the contiguous segment w of the
-// keys: it counts its digits (LDS atomics), a workgroup scan turns the
-// counts into offsets in (digit, wave) order, and the wave scatters its
-// segment 64 keys at a time, ranking equal digits by lane order (a 4-ballot
-// match), so equal counts keep their order.
+// 32-bit count, 8 bits a pass, as many passes as the largest count needs;
+// tmp[0, m) is the other buffer and cnt an LDS area of NT / 64 * 256 words.
+// Wave w owns the contiguous segment w of the keys: it counts its digits
+// (LDS atomics), a workgroup scan turns the counts into offsets in (digit,
+// wave) order, and the wave scatters its segment 64 keys at a time.  The
+// lanes of a group sharing my digit are the AND over its 8 bits of that
+// bit's ballot or its complement; a key goes to its digit's offset plus the
+// equal-digit lanes before it (so equal counts keep their order), and the
+// last of them advances the offset.  A wave's LDS operations take effect
+// in order, so the next group sees the advanced offsets.  The next 64 keys
+// are loaded while the current ones are placed.
 template <int NT>
 __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, uint32_t m, uint32_t wmax,
-                                                Shared& sh) {
+                                                Shared& sh, uint32_t* cnt) {
   constexpr uint32_t NW = NT / kWave;
+  constexpr uint32_t PER = NW * 256 / NT;  // counters per thread in the scan
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   uint32_t passes = 0;
-  while (passes < 8 && (wmax >> (4 * passes)) != 0) ++passes;
+  while (passes < 4 && (wmax >> (8 * passes)) != 0) ++passes;
   const uint32_t seg = (m + NW - 1) / NW;
   const uint32_t s0 = min(m, wave * seg), s1 = min(m, s0 + seg);
+  uint32_t* wc = cnt + wave * 256;
   uint64_t* src = key;
   uint64_t* dst = tmp;
-  uint32_t* cnt = sh.rcnt;
   for (uint32_t p = 0; p < passes; ++p) {
-    const uint32_t shift = 16 + 4 * p;
-    for (uint32_t i = tid; i < NW * 16; i += NT) cnt[i] = 0;
+    const uint32_t shift = 16 + 8 * p;
+    for (uint32_t i = tid; i < NW * 256; i += NT) cnt[i] = 0;
     __syncthreads();
-    for (uint32_t i = s0 + lane; i < s1; i += kWave) atomicAdd(&cnt[wave * 16 + ((uint32_t)(src[i] >> shift) & 15)], 1u);
-    __syncthreads();
-    // offsets in (digit, wave) order: thread d * NW + w takes counter (w, d)
-    const uint32_t w_of = tid % NW, d_of = tid / NW;
-    const uint32_t v = tid < NW * 16 ? cnt[w_of * 16 + d_of] : 0u;
-    uint32_t tot;
-    const uint32_t pre = block_exclusive_scan<NW>(v, sh.wtot, &tot);
-    __syncthreads();
-    if (tid < NW * 16) cnt[w_of * 16 + d_of] = pre;
-    __syncthreads();
-    for (uint32_t b = s0; b < s1; b += kWave) {
-      const uint32_t i = b + lane;
-      const bool valid = i < s1;
-      const uint64_t k = valid ? src[i] : 0ull;
-      const uint32_t d = (uint32_t)(k >> shift) & 15;
-      uint64_t match = __ballot(valid);
+    for (uint32_t i0 = s0; i0 < s1; i0 += 4 * kWave) {
+      uint64_t k[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool bit = (d >> q) & 1;
-        const uint64_t mb = __ballot(valid && bit);
-        match &= bit ? mb : ~mb;
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * kWave + lane;
+        k[u] = i < s1 ? src[i] : 0ull;
       }
-      const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
-      if (valid) dst[cnt[wave * 16 + d] + rank] = k;
-      if (valid && rank == 0) atomicAdd(&cnt[wave * 16 + d], (uint32_t)__popcll(match));
-      wave_sync();  // this wave's next group reads the advanced offsets
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * kWave + lane < s1) atomicAdd(&wc[(uint32_t)(k[u] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    // offsets in (digit, wave) order: thread t takes entries [PER t, PER t + PER)
+    // of that order, entry j being counter (wave j % NW, digit j / NW)
+    uint32_t v[PER], c = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+      const uint32_t j = PER * tid + q;
+      v[q] = cnt[(j % NW) * 256 + j / NW];
+      c += v[q];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan<NW>(c, sh.wtot, &tot);
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+      const uint32_t j = PER * tid + q;
+      cnt[(j % NW) * 256 + j / NW] = pre;
+      pre += v[q];
+    }
+    __syncthreads();
+    uint64_t kn = s0 + lane < s1 ? src[s0 + lane] : 0ull;
+    for (uint32_t b = s0; b < s1; b += kWave) {
+      const bool valid = b + lane < s1;
+      const uint64_t k = kn;
+      if (b + kWave + lane < s1) kn = src[b + kWave + lane];
+      const uint32_t d = valid ? (uint32_t)(k >> shift) & 255 : 256u;  // 256: no used digit
+      uint64_t match = ~0ull;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const bool on = (d >> q) & 1u;
+        const uint64_t B = __ballot(on);
+        match &= on ? B : ~B;
+      }
+      if (valid) {
+        const uint32_t slot = wc[d] + (uint32_t)__popcll(match & lanemask_lt());
+        dst[slot] = k;
+        if ((match >> lane) == 1ull) wc[d] = slot + 1;
+      }
     }
     __syncthreads();
     uint64_t* t2 = src;
@@ -318,10 +362,11 @@ __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, ui
   }
 }
 
+// lds_scratch: NT / 64 * 256 words of LDS free until the rounds.
 template <typename IdT, int NT>
 __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
                                            uint32_t A, uint32_t m, uint32_t wmax, const hf_codebook& book,
-                                           uint32_t* status) {
+                                           uint32_t* status, uint32_t* lds_scratch) {
   constexpr int NW = NT / kWave;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
@@ -378,11 +423,12 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     __syncthreads();
     for (uint32_t i = tid; i < m; i += NT) t.key[i] = t.mw[i];
   } else {
-    radix_sort_keys<NT>(t.key, t.mw, m, wmax, sh);
+    radix_sort_keys<NT>(t.key, t.mw, m, wmax, sh, lds_scratch);
   }
   __syncthreads();
 
   // ---- 3. GenerateCL rounds ------------------------------------------------
+  uint32_t nrounds = kRoundEndsMax + 1;  // rounds run by the workgroup (recorded up to kRoundEndsMax)
   if (sizeof(IdT) == 2 && m <= kOneWaveRoundsMax) {
     // tree in LDS, short runs: one wave runs the rounds
     if (wave == 0) rounds_one_wave(t, m, status);
@@ -390,6 +436,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   } else {
   // every lane tracks the queues: leaves [lc, m), internal nodes [ih, it)
   uint32_t lc = 0, ih = 0, it = 0;
+  nrounds = 0;
   for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
     if (round >= m) {  // every round creates at least one node: m - 1 rounds suffice
       if (tid == 0) raise_status(status, HF_ERR_INTERNAL);
@@ -404,16 +451,51 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
         wsum += leaf ? (t.key[li++] >> 16) : t.iw[ii++];
       }
     }
-    // a = leaves in [lc, m) with weight <= t: the lane seeing the boundary records it
-    for (uint32_t p = lc + tid; p <= m; p += NT) {
-      const bool below = p == lc || (t.key[p - 1] >> 16) <= wsum;
-      const bool above = p == m || (t.key[p] >> 16) > wsum;
-      if (below && above) sh.a = p - lc;
+    // a = leaves in [lc, m) with weight <= t (a prefix of the sorted rest):
+    // the blocks of `step` leaves lying wholly below t, then the leaves below
+    // t inside the next block, each counted in one barrier
+    uint32_t a;
+    {
+      const uint32_t R = m - lc, step = (R + NT - 1) / NT;
+      const bool whole = tid * step < R && (t.key[lc + min(R, (tid + 1) * step) - 1] >> 16) <= wsum;
+      const uint32_t c1 = (uint32_t)__syncthreads_count(whole);
+      const uint32_t base = lc + c1 * step;
+      const bool part = tid < step && base + tid < m && (t.key[base + tid] >> 16) <= wsum;
+      const uint32_t c2 = (uint32_t)__syncthreads_count(part);
+      a = min(R, c1 * step + c2);
     }
-    __syncthreads();
-    const uint32_t a = sh.a, b = it - ih;
+    const uint32_t b = it - ih;
     const uint32_t total = a + b, pairs = total >> 1;
-    // Merge Path: leaves precede internal nodes of equal weight
+    // Merge Path: leaves precede internal nodes of equal weight.  A long
+    // merge is cut into NT equal output ranges: one binary search along the
+    // range's first diagonal, then a sequential merge of the range;
+    // otherwise each element finds its position in the other run.
+    if (total > 2 * NT) {
+      const uint32_t per = (total + NT - 1) / NT;
+      const uint32_t d0 = min(total, tid * per), d1 = min(total, d0 + per);
+      uint32_t lo = d0 > b ? d0 - b : 0u, hi = min(d0, a);
+      while (lo < hi) {  // leaves [0, i) and internal nodes [0, d0 - i) come first
+        const uint32_t md = (lo + hi) >> 1;
+        if ((t.key[lc + md] >> 16) <= t.iw[ih + d0 - md - 1]) lo = md + 1;
+        else hi = md;
+      }
+      uint32_t i = lo, j = d0 - lo;
+      uint64_t wl = i < a ? t.key[lc + i] >> 16 : ~0ull;
+      uint64_t wi = j < b ? t.iw[ih + j] : ~0ull;
+      for (uint32_t d = d0; d < d1; ++d) {
+        if (i < a && (j >= b || wl <= wi)) {
+          t.mw[d] = wl;
+          t.mid[d] = (IdT)(lc + i);
+          ++i;
+          wl = i < a ? t.key[lc + i] >> 16 : ~0ull;
+        } else {
+          t.mw[d] = wi;
+          t.mid[d] = (IdT)(m + ih + j);
+          ++j;
+          wi = j < b ? t.iw[ih + j] : ~0ull;
+        }
+      }
+    } else {
     for (uint32_t j = tid; j < a; j += NT) {
       const uint64_t w = t.key[lc + j] >> 16;
       uint32_t lo = ih, hi = it;
@@ -438,6 +520,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
       t.mw[pos] = w;
       t.mid[pos] = (IdT)(m + ih + q);
     }
+    }
     __syncthreads();
     // Meld consecutive pairs; an odd last node stays in its queue
     for (uint32_t p = tid; p < pairs; p += NT) {
@@ -451,18 +534,36 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     lc += a - (carry_leaf ? 1u : 0u);
     ih += b - (carry_int ? 1u : 0u);
     it += pairs;
+    if (tid == 0 && round < kRoundEndsMax) sh.rend[round] = it;
+    nrounds = round + 1;
     __syncthreads();
   }
   }
 
-  // ---- 4. depths by pointer jumping ----------------------------------------
+  // ---- 4. depths of internal nodes ------------------------------------------
+  // A node's parent is created in a later round, so with the round ends
+  // recorded the depths follow round by round from the last (the root, at
+  // depth 0); otherwise by pointer jumping over parent links.
   const uint32_t nint = m - 1, root = m - 2;
+  uint16_t* dc = t.dA;
+  if (nrounds <= kRoundEndsMax) {
+    if (tid == 0) dc[root] = 0;
+    __syncthreads();
+    for (int r = (int)nrounds - 1; r >= 0; --r) {
+      const uint32_t k0 = r > 0 ? sh.rend[r - 1] : 0u, k1 = sh.rend[r];
+      for (uint32_t k = k0 + tid; k < k1; k += NT)
+        if (k != root) {
+          const uint32_t d = (uint32_t)dc[(uint32_t)t.par[m + k]] + 1;
+          dc[k] = (uint16_t)(d < 0xFFFFu ? d : 0xFFFFu);
+        }
+      __syncthreads();
+    }
+  } else {
   for (uint32_t k = tid; k < nint; k += NT) {
     t.dA[k] = (k == root) ? 0 : 1;
     t.nA[k] = (IdT)((k == root) ? root : (uint32_t)t.par[m + k]);
   }
   __syncthreads();
-  uint16_t* dc = t.dA;
   uint16_t* dn = t.dB;
   IdT* nc = t.nA;
   IdT* nn = t.nB;
@@ -484,10 +585,12 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
       break;
     }
   }
+  }
 
   // ---- 5a. leaf lengths, counts per length, total bits ----------------------
   uint64_t bits = 0;
   uint32_t my_max = 0, my_min = 0xFFFFFFFFu;
+#pragma unroll 2
   for (uint32_t i0 = 0; i0 < m; i0 += NT) {
     const uint32_t i = i0 + tid;
     const bool valid = i < m;
@@ -545,52 +648,51 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   }
 
   // ---- 5c. rank within each length in symbol order -------------------------
+  // Wave w takes a contiguous segment of compact indices.  In each 64-symbol
+  // group the lanes sharing my length are the AND over the length's 7 bits
+  // of that bit's ballot or its complement (past the segment lanes carry
+  // length 0, which no used symbol has); the group's last lane of each length
+  // updates that length's count (pass 1) or next rev slot (pass 2).  A
+  // wave's LDS operations take effect in order, so the next group sees it.
   const uint32_t seg = ((m + NT - 1) / NT) * kWave;
   const uint32_t sbeg = min(m, wave * seg), send = min(m, sbeg + seg);
-  uint32_t creg = 0;  // lane l-1 counts length l
-  for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
-    const uint32_t u = u0 + lane;
-    const bool valid = u < send;
-    const uint32_t l = valid ? t.clu[u] : 0;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
-      const uint64_t mask = __ballot(valid && l == lv);
-      if (lane == lv - 1) creg += (uint32_t)__popcll(mask);
-      pending &= ~mask;
-    }
-  }
-  sh.cntw[wave][lane + 1] = creg;
-  __syncthreads();
-  if (tid >= 1 && tid <= kMaxLen) {
-    uint32_t run = sh.entry[tid];
-    for (int w = 0; w < NW; ++w) {
-      const uint32_t c = sh.cntw[w][tid];
-      sh.cntw[w][tid] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
-  uint32_t breg = sh.cntw[wave][lane + 1];  // next rev slot of length lane+1
-  for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
-    const uint32_t u = u0 + lane;
-    const bool valid = u < send;
-    const uint32_t l = valid ? t.clu[u] : 0;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)l, leader);
-      const uint64_t mask = __ballot(valid && l == lv);
-      const uint32_t slot0 = (uint32_t)__builtin_amdgcn_readlane((int)breg, (int)lv - 1);
-      if (valid && l == lv) {
-        const uint32_t pos = slot0 + (uint32_t)__popcll(mask & lanemask_lt());
+  uint32_t* wc = sh.cntw[wave];  // [kMaxLen + 1] this wave's count, then next slot, per length
+  for (uint32_t l = lane; l <= kMaxLen; l += kWave) wc[l] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
+      const uint32_t u = u0 + lane;
+      const bool valid = u < send;
+      const uint32_t l = valid ? t.clu[u] : 0u;
+      uint64_t eq = ~0ull;
+#pragma unroll
+      for (int bit = 0; bit < 7; ++bit) {
+        const bool on = (l >> bit) & 1u;
+        const uint64_t B = __ballot(on);
+        eq &= on ? B : ~B;
+      }
+      const bool last = valid && (eq >> lane) == 1ull;
+      if (pass == 0) {
+        if (last) wc[l] += (uint32_t)__popcll(eq);
+      } else if (valid) {
+        const uint32_t pos = wc[l] + (uint32_t)__popcll(eq & lanemask_lt());
         const uint32_t s = (uint32_t)t.usym[u];
         book.rev[pos] = s;
-        book.cw[s] = sh.first[lv] + (pos - sh.entry[lv]);
+        book.cw[s] = sh.first[l] + (pos - sh.entry[l]);
+        if (last) wc[l] = pos + 1;
       }
-      if (lane == lv - 1) breg += (uint32_t)__popcll(mask);
-      pending &= ~mask;
+    }
+    if (pass == 0) {
+      __syncthreads();
+      // slots: codes shorter than l, then earlier waves' codes of length l
+      if (tid >= 1 && tid <= kMaxLen) {
+        uint32_t run = sh.entry[tid];
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = sh.cntw[w][tid];
+          sh.cntw[w][tid] = run;
+          run += c;
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -894,10 +996,10 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   // The lanes of a 64-symbol chunk that share my length are the AND over
   // the length's 7 bits of that bit's ballot or its complement (unused
   // lanes carry length 0, which no used symbol has).  The last lane of each
-  // length advances that length's next rev slot.
+  // length advances that length's next rev slot (a wave's LDS operations
+  // take effect in order, so the next chunk sees it).
   uint32_t* ns = (uint32_t*)L.mw + 2048;  // [kMaxLen + 1] next rev slot per length
   ns[len] = below;
-  wave_sync();
   for (uint32_t u0 = 0; u0 < m; u0 += kWave) {
     const uint32_t u = u0 + lane;
     const bool valid = u < m;
@@ -916,7 +1018,6 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
       book.cw[s] = fl[l] + (pos - el[l]);
       if ((eq >> lane) == 1ull) ns[l] = pos + 1;
     }
-    wave_sync();
   }
 }
 
@@ -928,6 +1029,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
   const uint32_t tid = threadIdx.x;
   uint32_t c = 0, hmax = 0;
   uint64_t wsum = 0;
+#pragma unroll 8
   for (uint32_t s = tid; s < A; s += NT) {
     const uint32_t h = hist[s];
     c += (h != 0);
@@ -966,7 +1068,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = t.dA + kCbLdsMaxUsed;
     t.nA = t.dB + kCbLdsMaxUsed;
     t.nB = t.nA + kCbLdsMaxUsed;
-    build_book<uint16_t, NT>(t, L.sh, hist, A, m, wmax, book, status);
+    build_book<uint16_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw);
   } else {
     const GlobalLayout G = global_layout(A);
     Tree<uint32_t> t;
@@ -981,7 +1083,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = (uint16_t*)(ws + G.dB);
     t.nA = (uint32_t*)(ws + G.nA);
     t.nB = (uint32_t*)(ws + G.nB);
-    build_book<uint32_t, NT>(t, L.sh, hist, A, m, wmax, book, status);
+    build_book<uint32_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw);
   }
 }
 

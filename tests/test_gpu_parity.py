@@ -230,6 +230,14 @@ def _hist_cases():
     cases["m2000_ties"] = np.concatenate([rng.choice(np.array([1, 2, 2, 3, 7], np.uint32), size=2000),
                                           np.zeros(96, np.uint32)])
     cases["m3000_geom"] = np.maximum(1, (1e9 * 0.995 ** np.arange(3000))).astype(np.uint32)
+    # more than 4096 used: tree in the workspace; Zipf counts up to 2^28 take
+    # seven 4-bit sort passes; geometric counts need more rounds than are
+    # recorded (depths by pointer jumping)
+    p = np.arange(1, 65537, dtype=np.float64) ** -1.05
+    cases["zipf65536"] = np.maximum(1, np.round(p / p.sum() * (1 << 28))).astype(np.uint32)
+    h = np.zeros(16384, np.uint32)
+    h[rng.choice(16384, size=6000, replace=False)] = np.maximum(1, (1e9 * 0.9975 ** np.arange(6000))).astype(np.uint32)
+    cases["m6000_geom_global"] = h
     # the sum of counts just below / at 2^32 - 1 (register path / general path)
     h = np.zeros(1024, np.uint32); h[:200] = 1; h[500] = 0xFFFFFFFE - 200 - 7; h[501:508] = 1
     assert int(h.sum(dtype=np.uint64)) == 0xFFFFFFFE
