@@ -44,8 +44,11 @@ constexpr int kPreThreads = 256;
 constexpr int kPreWaves = kPreThreads / kWave;
 
 // Encoding modes, chosen per launch from the codebook's longest code:
-//   kModeTable : codes <= 27 bits, alphabet <= 8192: packed (cw << 5 | cl)
-//                table and tile buffer in LDS;
+//   kModeTable : codes <= 27 bits, alphabet <= 8192: packed table (code
+//                left-aligned, 32 - cl in the low 5 bits) and tile buffer
+//                in LDS;
+//   kModeSplit : codes of 28 .. 31 bits, alphabet <= 4096: left-aligned
+//                codes and a byte table of 32 - cl in LDS;
 //   kModeGlobal: codes <= 32 bits: codebook read from global memory (L2),
 //                tile buffer in LDS;
 //   kModeWide  : longer codes: codebook from global memory and bits ORed
@@ -53,6 +56,16 @@ constexpr int kPreWaves = kPreThreads / kWave;
 constexpr int kModeTable = 0;
 constexpr int kModeGlobal = 1;
 constexpr int kModeWide = 2;
+constexpr int kModeSplit = 3;
+constexpr uint32_t kSplitMaxLen = 31;  // 32 - cl >= 1 keeps the word-completion test exact
+constexpr uint32_t kSplitMaxAlphabet = 4096;
+
+// LDS words of the table modes' tables for an alphabet: A + 1 entries, and
+// A + 1 bytes for the split mode up to 4096 symbols (none above 8192).
+__host__ __device__ inline uint32_t table_words(uint32_t A) {
+  if (A > kTableMaxAlphabet) return 0u;
+  return (A + 1) + (A <= kSplitMaxAlphabet ? (A + 4) / 4 : 0u);
+}
 
 struct SlabArgs {
   const void* sym;
@@ -242,22 +255,33 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     const uint64_t Gt = G + run;            // the tile's first bit in the stream
     const uint32_t q = (uint32_t)(Gt & 31);  // ... and its offset in buf[0]
 
-    // ---- lookup: packed entries (table mode) or symbols; lane bit count ----
+    // ---- lookup: table entries (table modes) or symbols; lane bit count ----
+    // ent: the code left-aligned (table mode: with 32 - cl in its low 5
+    // bits); fsh: the split mode's 32 - cl (0: no code)
+    constexpr bool kTab = MODE == kModeTable || MODE == kModeSplit;
+    const uint8_t* tabf = (const uint8_t*)(tab + a.A + 1);
     uint32_t ent[NS];
+    uint32_t fsh[MODE == kModeSplit ? NS : 1];
     uint32_t L = 0;
     bool bad = false;
     bool full_tile = false;
-    if (MODE == kModeTable && s_lo + (uint64_t)(t + 1) * T <= s_hi) {
-      // whole tile inside the slab: no per-symbol branches; tab[A] = 0 catches
-      // symbols outside the alphabet, a zero entry marks a symbol without code
-      // (a zero entry counts 32 bits here; the slab's total then differs
-      // from the prepass's, which flags it at the end of the slab)
+    if (kTab && s_lo + (uint64_t)(t + 1) * T <= s_hi) {
+      // whole tile inside the slab: no per-symbol branches; entry A is empty
+      // and catches symbols outside the alphabet, an empty entry marks a
+      // symbol without code (it counts 32 bits here; the slab's total then
+      // differs from the prepass's, which flags it at the end of the slab)
       uint32_t fsum = 0;
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i) {
-        const uint32_t e = tab[min(raw.symbol(i), a.A)];
+        const uint32_t k = min(raw.symbol(i), a.A);
+        const uint32_t e = tab[k];
         ent[i] = e;
-        fsum += e & 31;
+        if (MODE == kModeSplit) {
+          fsh[i] = tabf[k];
+          fsum += fsh[i];
+        } else {
+          fsum += e & 31;
+        }
       }
       L = 32 * NS - fsum;
       full_tile = true;
@@ -272,6 +296,17 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
             bad |= e == 0;
             ent[i] = e;
             L += e ? 32 - (e & 31) : 0u;
+          }
+        } else if (MODE == kModeSplit) {
+          ent[i] = 0;
+          fsh[i] = 0;
+          if (i < nvalid) {
+            const uint32_t k = min(sv, a.A);
+            const uint32_t f = tabf[k];
+            bad |= f == 0;
+            ent[i] = tab[k];
+            fsh[i] = f;
+            L += f ? 32 - f : 0u;
           }
         } else {
           ent[i] = 0xFFFFFFFFu;
@@ -292,7 +327,7 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     if (!last_tile) raw.load(a.sym, s0 + T, s_hi, a.vec_ok != 0);  // next tile, in flight meanwhile
 
     // ---- reduce-merge ---------------------------------------------------------
-    if (MODE == kModeTable) {
+    if (kTab) {
       // pend's low nb bits are this lane's bits of word wp so far (zeros for
       // the bits of earlier lanes).  A code of len = 32 - f bits completes the
       // word when nb >= f: the word is then bits [nb, nb + 32) of (pend:e), and
@@ -301,7 +336,9 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       // bits, f) and the new count is (nb - f) mod 32, which is below nb
       // exactly when a word completes (5 <= f <= 31).  At most one word
       // completes per code (<= 27 bits on <= 31 pending); the OR always
-      // issues, into this lane's dummy word when none does.
+      // issues, into this lane's dummy word when none does.  The split mode
+      // reads f from its byte table (1 <= f, so the test stays exact) and its
+      // codes have no low bits to shift out.
       uint32_t pend = 0;
       uint32_t nb = (P + q) & 31;
       uint32_t* wp = buf + ((P + q) >> 5);
@@ -310,10 +347,11 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
 #pragma unroll
         for (uint32_t i = 0; i < NS; ++i) {
           const uint32_t e = ent[i];
+          const uint32_t f = MODE == kModeSplit ? fsh[i] : e;  // shift: its low 5 bits
           const uint32_t word = __builtin_amdgcn_alignbit(pend, e, nb);
-          const uint32_t nb2 = (nb - e) & 31;
+          const uint32_t nb2 = (nb - f) & 31;
           const bool full = nb2 < nb;
-          pend = __builtin_amdgcn_alignbit(pend, e, e);
+          pend = __builtin_amdgcn_alignbit(pend, e, f);
           nb = nb2;
           atomicOr(full ? wp : sink, word);
           wp += full ? 1 : 0;
@@ -322,8 +360,8 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
 #pragma unroll
         for (uint32_t i = 0; i < NS; ++i) {
           const uint32_t e = ent[i];
-          if (e == 0) continue;  // past the slab's end, or a symbol without code (flagged)
-          const uint32_t f = e & 31;
+          const uint32_t f = MODE == kModeSplit ? fsh[i] : (e & 31);
+          if (f == 0) continue;  // past the slab's end, or a symbol without code (flagged)
           const uint32_t word = __builtin_amdgcn_alignbit(pend, e, nb);
           const bool full = nb >= f;
           pend = __builtin_amdgcn_alignbit(pend, e, f);
@@ -421,7 +459,31 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       sh.tailw = 0;
     }
   }
-  if (MODE == kModeTable && tid == 0 && run != expect) raise_status(a.status, HF_ERR_SYMBOL);
+  if ((MODE == kModeTable || MODE == kModeSplit) && tid == 0 && run != expect)
+    raise_status(a.status, HF_ERR_SYMBOL);
+}
+
+__device__ __forceinline__ int encode_mode(uint32_t A, uint32_t lmax) {
+  if (A <= kTableMaxAlphabet && lmax <= kPackedMaxLen) return kModeTable;
+  if (A <= kSplitMaxAlphabet && lmax <= kSplitMaxLen) return kModeSplit;
+  return lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide;
+}
+
+// The table modes' LDS tables: tab[s] is the packed entry (table mode) or the
+// left-aligned code (split mode, with 32 - cl in the bytes after tab[A]);
+// entry A and the entries of unused symbols are empty.
+__device__ __forceinline__ void build_tables(const EncArgs& a, int mode, uint32_t* tab) {
+  if (mode != kModeTable && mode != kModeSplit) return;
+  uint8_t* tabf = (uint8_t*)(tab + a.A + 1);
+  for (uint32_t s = threadIdx.x; s <= a.A; s += kEncThreads) {
+    const uint32_t l = s < a.A ? a.cl[s] : 0u;
+    if (mode == kModeTable) {
+      tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
+    } else {
+      tab[s] = l ? (uint32_t)a.cw[s] << (32 - l) : 0u;
+      tabf[s] = (uint8_t)(l ? 32 - l : 0u);
+    }
+  }
 }
 
 template <int R, int SB>
@@ -432,18 +494,13 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   const uint32_t tid = threadIdx.x;
   const uint32_t g = blockIdx.x;
   const uint32_t lmax = (uint32_t)a.info[1];
-  const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
-  const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
-  // LDS: [tile buffer: T + 8 words, 16-byte aligned][table: A + 1 entries,
-  // if A <= 8192][kEncThreads dummy words]
+  const int mode = encode_mode(a.A, lmax);
+  // LDS: [tile buffer: T + 8 words, 16-byte aligned][tables, if A <= 8192:
+  // A + 1 words and A + 1 bytes][kEncThreads dummy words]
   uint32_t* buf = lds;
   uint32_t* tab = lds + T + 8;
-  uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
-  if (mode == kModeTable)
-    for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
-      const uint32_t l = s < a.A ? a.cl[s] : 0u;
-      tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
-    }
+  uint32_t* dummy = tab + table_words(a.A);
+  build_tables(a, mode, tab);
   if (mode != kModeWide)
     for (uint32_t i = tid; i < T + 8; i += kEncThreads) buf[i] = 0;
   // this slab's first bit: the bit totals of all earlier slabs
@@ -460,6 +517,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
 #pragma unroll
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
   if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
+  else if (mode == kModeSplit) encode_slab<R, SB, kModeSplit>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
   else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
 }
@@ -529,16 +587,11 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   a.status = bs.status;
   a.vec_ok = ((uintptr_t)bs.sym % 16) == 0 ? 1u : 0u;
   const uint32_t lmax = (uint32_t)a.info[1];
-  const bool table = a.A <= kTableMaxAlphabet && lmax <= kPackedMaxLen;
-  const int mode = table ? kModeTable : (lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide);
+  const int mode = encode_mode(a.A, lmax);
   uint32_t* buf = lds;  // same layout as encode_kernel
   uint32_t* tab = lds + T + 8;
-  uint32_t* dummy = tab + (a.A <= kTableMaxAlphabet ? a.A + 1 : 0u);
-  if (mode == kModeTable)
-    for (uint32_t s = tid; s <= a.A; s += kEncThreads) {
-      const uint32_t l = s < a.A ? a.cl[s] : 0u;
-      tab[s] = l ? pack_entry((uint32_t)a.cw[s], l) : 0u;
-    }
+  uint32_t* dummy = tab + table_words(a.A);
+  build_tables(a, mode, tab);
   if (mode != kModeWide)
     for (uint32_t i = tid; i < T + 8; i += kEncThreads) buf[i] = 0;
   uint64_t G = 0;
@@ -555,10 +608,12 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
   if (bs.sym_bytes == 1) {
     if (mode == kModeTable) encode_slab<R, 1, kModeTable>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else if (mode == kModeSplit) encode_slab<R, 1, kModeSplit>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
     else if (mode == kModeGlobal) encode_slab<R, 1, kModeGlobal>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
     else encode_slab<R, 1, kModeWide>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
   } else {
     if (mode == kModeTable) encode_slab<R, 2, kModeTable>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
+    else if (mode == kModeSplit) encode_slab<R, 2, kModeSplit>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
     else if (mode == kModeGlobal) encode_slab<R, 2, kModeGlobal>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
     else encode_slab<R, 2, kModeWide>(a, tab, buf, dummy, sh, g, G, bs.slab_bits[g]);
   }
@@ -586,7 +641,7 @@ EncodeFn pick(uint32_t r, uint32_t sb) {
 
 size_t encode_lds_bytes(uint32_t A, uint32_t r) {
   const size_t T = (size_t)kEncThreads << r;
-  return 4 * (kEncThreads + (A <= kTableMaxAlphabet ? (size_t)A + 1 : 0) + T + 8);
+  return 4 * (kEncThreads + (size_t)table_words(A) + T + 8);
 }
 
 // Resident workgroups per CU, cached per kernel and LDS size.
@@ -692,7 +747,7 @@ hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_i
                                hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
   if (nitems == 0) return hipSuccess;
   const size_t T = (size_t)kEncThreads << r;
-  const size_t lds = 4 * (T + 8 + (max_alphabet <= kTableMaxAlphabet ? (size_t)max_alphabet + 1 : 0) + kEncThreads);
+  const size_t lds = 4 * (T + 8 + (size_t)table_words(max_alphabet) + kEncThreads);
   using Fn = void (*)(const BatchStream*, const uint32_t*, const uint32_t*);
   Fn fn;
   switch (r) {

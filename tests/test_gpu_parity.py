@@ -295,12 +295,15 @@ def _fib_stream(nfib: int, base: int, seed: int) -> np.ndarray:
     return x
 
 
-@pytest.mark.parametrize("nfib,mode", [(30, "codebook from global memory, 29-bit codes"),
-                                       (33, "codebook from global memory, 32-bit codes"),
-                                       (34, "codes over 32 bits, bits ORed into the output")])
-def test_encode_long_codes(nfib, mode):
-    x = _fib_stream(nfib, 200, nfib)
-    ref_h = oracle.histogram(x, 1024)
+@pytest.mark.parametrize("nfib,A,base,mode", [(29, 1024, 200, "split tables, 28-bit codes"),
+                                              (30, 1024, 200, "split tables, 29-bit codes"),
+                                              (32, 4096, 4000, "split tables, 31-bit codes"),
+                                              (30, 8192, 5000, "codebook from global memory, 29-bit codes"),
+                                              (33, 1024, 200, "codebook from global memory, 32-bit codes"),
+                                              (34, 1024, 200, "codes over 32 bits, bits ORed into the output")])
+def test_encode_long_codes(nfib, A, base, mode):
+    x = _fib_stream(nfib, base, nfib)
+    ref_h = oracle.histogram(x, A)
     ref = oracle.codebook(ref_h)
     assert ref.lmax == nfib - 1
     book, code = gpu_book(ref_h)
@@ -335,6 +338,17 @@ def test_encode_flags_symbol_without_code():
     book, _ = gpu_book(oracle.histogram(x, 1024))
     y = x.copy()
     y[12345] = 1000  # no code in this book
+    _, _, code = gpu_encode(y, book, 4096)
+    assert code == hf.HF_ERR_SYMBOL
+
+
+@pytest.mark.parametrize("at", [5, 700_000, 2_178_307])  # first tile, middle, last symbol
+def test_encode_split_tables_flag_symbol_without_code(at):
+    x = _fib_stream(30, 200, 3)
+    book, _ = gpu_book(oracle.histogram(x, 1024))
+    assert int(book.info[1].item()) == 29
+    y = x.copy()
+    y[at % y.size] = 900  # no code in this book
     _, _, code = gpu_encode(y, book, 4096)
     assert code == hf.HF_ERR_SYMBOL
 
