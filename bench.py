@@ -43,9 +43,12 @@ def parse():
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
                         "serve: a Poisson trace of requests, continuous batching vs one request at a time")
-    p.add_argument("--requests", type=int, default=200, help="serve mode: requests in the trace")
-    p.add_argument("--qps", type=float, default=2000.0, help="serve mode: mean arrival rate")
-    p.add_argument("--arena-gib", type=float, default=48.0, help="serve mode: HBM arena for outputs and state")
+    p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
+    p.add_argument("--rho", default="0.5,0.8",
+                   help="serve mode: offered loads as fractions of the measured saturated capacity")
+    p.add_argument("--qps", type=float, default=0.0,
+                   help="serve mode: a fixed mean arrival rate instead of the --rho points (0 = use --rho)")
+    p.add_argument("--arena-gib", type=float, default=32.0, help="serve mode: HBM arena for outputs and state")
     p.add_argument("--streams", type=int, default=512, help="batch mode: streams per step")
     p.add_argument("--tuning", default=os.path.join(ROOT, "paper_2010_10039_amd", "tuning_mi355x.json"),
                    help="batch mode: autotuner table (tuned on the device when the file is missing)")
@@ -279,12 +282,15 @@ def run_batch(args):
 
 
 def run_serve(args):
-    """Served workload: a trace of `args.requests` requests with Poisson
-    arrivals at `args.qps` (sizes log-uniform in 1 MiB..512 MiB, u8 or u16,
-    alphabets 256..65536, skew-normal or Zipf), served in real time by the
-    continuous-batching loop and, on the same trace, by a server that runs
-    one request at a time with plain launches.  Inputs are in HBM before the
-    trace starts (as if produced there by an upstream stage)."""
+    """Served workload: `args.requests` compression requests (sizes
+    log-uniform in 1 MiB..512 MiB, u8 with alphabet 256 or u16 with alphabets
+    1024..65536, skew-normal or Zipf), their inputs in HBM before the trace
+    starts (as if produced there by an upstream stage).  First the saturated
+    capacity: every request queued at t = 0, served by the continuous-
+    batching loop.  Then, for each offered load rho, Poisson arrivals at
+    rho x capacity / mean request size, served in real time by the
+    continuous-batching loop and, on the same arrivals, by a server that runs
+    one request at a time with plain launches."""
     import torch
 
     from paper_2010_10039_amd import serve, workloads
@@ -292,18 +298,25 @@ def run_serve(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    trace = workloads.served_requests(args.requests, seed=2000, qps=args.qps, device="cuda")
+    trace = workloads.served_requests(args.requests, seed=2000, qps=1.0, device="cuda")
     torch.cuda.synchronize()
-    total = sum(x.numel() * x.element_size() for _, x, _, _ in trace)
-    log(f"generated {len(trace)} requests, {total} bytes, in {time.perf_counter() - t0:.1f}s; "
-        f"trace spans {trace[-1][0] * 1e3:.1f} ms")
+    nbytes = [x.numel() * x.element_size() for _, x, _, _ in trace]
+    total = sum(nbytes)
+    mean_bytes = total / len(trace)
+    log(f"generated {len(trace)} requests, {total} bytes (mean {mean_bytes / 1e6:.1f} MB), "
+        f"in {time.perf_counter() - t0:.1f}s")
     cap = int(args.arena_gib * (1 << 30))
+    servers = (("continuous_batching", dict(slots=3, max_batch=32)),
+               ("plain_one_at_a_time", dict(slots=1, max_batch=1, use_batch=False)))
 
-    def make():
-        return [serve.Request(i, x.numel(), x.element_size(), A, t, chunk=args.chunk, sym=x)
-                for i, (t, x, A, _) in enumerate(trace)]
+    def make(arrivals):
+        return [serve.Request(i, x.numel(), x.element_size(), A, arrivals[i], chunk=args.chunk, sym=x)
+                for i, (_, x, A, _) in enumerate(trace)]
 
-    def stats(loop, reqs):
+    def run(arrivals, kw):
+        reqs = make(arrivals)
+        loop = serve.serve(reqs, cap, **kw)
+        torch.cuda.synchronize()
         bad = [r.rid for r in reqs if r.status != 0]
         if bad:
             raise SystemExit(f"served requests failed: {bad[:10]}")
@@ -315,41 +328,49 @@ def run_serve(args):
                 "max_concurrent_batches": loop.max_busy}
 
     # warm up both servers on a short prefix (kernels, allocator, staging)
-    for kw in (dict(slots=3, max_batch=32), dict(slots=1, max_batch=1, use_batch=False)):
-        serve.serve(make()[:8], cap, **kw)
+    for _, kw in servers:
+        serve.serve(make([0.0] * len(trace))[:8], cap, **kw)
     torch.cuda.synchronize()
-    res = {}
-    for name, kw in (("continuous_batching", dict(slots=3, max_batch=32)),
-                     ("plain_one_at_a_time", dict(slots=1, max_batch=1, use_batch=False))):
-        reqs = make()
-        loop = serve.serve(reqs, cap, **kw)
-        torch.cuda.synchronize()
-        res[name] = stats(loop, reqs)
-        log(f"{name}: {res[name]}")
-    cb, pl = res["continuous_batching"], res["plain_one_at_a_time"]
+    if args.qps > 0:
+        loads = [("qps", args.qps)]
+    else:
+        saturated = {name: run([0.0] * len(trace), kw) for name, kw in servers}
+        for name, r in saturated.items():
+            log(f"saturated {name}: {r}")
+        capacity = saturated["continuous_batching"]["gbs"]
+        loads = [("rho", float(v)) for v in args.rho.split(",")]
+    points = []
+    for kind, v in loads:
+        qps = v if kind == "qps" else v * capacity * 1e9 / mean_bytes
+        arrivals = workloads.poisson_arrivals(len(trace), qps, seed=7)
+        pt = {"offered_qps": round(qps, 1), "offered_gbs": round(qps * mean_bytes / 1e9, 2)}
+        if kind == "rho":
+            pt["rho"] = v
+        for name, kw in servers:
+            pt[name] = run(arrivals, kw)
+        log(f"load point {pt}")
+        points.append(pt)
+    last = points[-1]["continuous_batching"]
+    config = {"workload": f"served_{len(trace)}_requests_1MiB_512MiB", "requests": len(trace),
+              "total_bytes": total, "mean_request_bytes": round(mean_bytes),
+              "p50_ms": last["p50_ms"], "p99_ms": last["p99_ms"], "points": points}
+    if args.qps <= 0:
+        config["capacity_gbs"] = capacity
+        config["saturated"] = saturated
     return {
         "metric": "served encode GB/s of input symbols, p50/p99 latency",
-        "value": cb["gbs"],
+        "value": last["gbs"],
         "unit": "GB/s",
         "n_gpus": 1,
-        "steps": 1,
+        "steps": len(points),
         "warmup": 1,
-        "ms_per_step": cb["span_ms"],
+        "ms_per_step": last["span_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8+u16",
         "data": "synthetic",
-        "config": {
-            "workload": f"served_{len(trace)}_requests_1MiB_512MiB_qps{args.qps:g}",
-            "requests": len(trace),
-            "total_bytes": total,
-            "qps": args.qps,
-            "p50_ms": cb["p50_ms"],
-            "p99_ms": cb["p99_ms"],
-            "continuous_batching": cb,
-            "plain_one_at_a_time": pl,
-        },
+        "config": config,
         "roofline": None,
         "cpu_baseline": None,
     }
