@@ -432,7 +432,7 @@ def main():
     m, lmax, total_bits = int(info[0]), int(info[1]), int(info[2])
     log(f"warmup done: m={m} Lmax={lmax} beta={total_bits / n:.4f}")
 
-    def stamps(stages, steps):
+    def timer_events(stages, steps):
         ev = {s: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(steps)] for s in stages}
         for s in stages:  # materialize the event handles before handing them to libhf
@@ -441,9 +441,9 @@ def main():
                 b.record()
         return ev
 
-    # Timed steps: the encode kernel's own dispatch carries a start/stop
-    # event pair (the roofline's per-launch duration); no other packets.
-    ev = stamps(("encode",), args.steps)
+    # Timed steps: an event pair around each encode kernel (the roofline's
+    # per-launch duration); the other stages carry no event packets here.
+    ev = timer_events(("encode",), args.steps)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
@@ -456,8 +456,8 @@ def main():
     hf.raise_on_status(enc.status, "timed steps")
     ms_per_step = start.elapsed_time(stop) / args.steps
     stage_ms = {"encode": sum(a.elapsed_time(b) for a, b in ev["encode"]) / args.steps}
-    # the other stages' main kernels, stamped in separate (untimed) steps
-    ev_other = stamps(("hist", "codebook"), args.steps)
+    # the other stages' main kernels, timed in separate (untimed) steps
+    ev_other = timer_events(("hist", "codebook"), args.steps)
     for k in range(args.steps):
         enc.run(d, timers={s: ev_other[s][k] for s in ev_other})
     torch.cuda.synchronize()

@@ -282,23 +282,14 @@ hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* 
     return HF_ERR_LAUNCH;
   if (hf::launch_batch_codebook(d_streams, nstreams, st) != hipSuccess) return HF_ERR_LAUNCH;
   if (hf::launch_batch_slab_bits(d_streams, d_item_stream, nitems, st) != hipSuccess) return HF_ERR_LAUNCH;
-  int first = -1, last = -1;
-  for (int k = 0; k < kEncGroups; ++k)
-    if (p.enc_count[k]) {
-      if (first < 0) first = k;
-      last = k;
-    }
-  if (first < 0) {
-    timer.before(st);
-    timer.after(st);
-  }
+  timer.before(st);
   for (int k = 0; k < kEncGroups; ++k) {
     if (!p.enc_count[k]) continue;
     if (hf::launch_batch_encode(d_streams, d_item_stream, d_enc_items + p.enc_start[k], p.enc_count[k],
-                                kRs[k / 3], kAlphaClasses[k % 3], st, timer.start_if(k == first),
-                                timer.stop_if(k == last)) != hipSuccess)
+                                kRs[k / 3], kAlphaClasses[k % 3], st) != hipSuccess)
       return HF_ERR_LAUNCH;
   }
+  timer.after(st);
   return HF_OK;
 }
 

@@ -1125,8 +1125,11 @@ size_t codebook_workspace_bytes(uint32_t alphabet) {
 hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
   (void)ws_bytes;
-  return launch_stamped(codebook_kernel<1024>, dim3(1), dim3(1024), 0, stream, timer.ev_before, timer.ev_after,
-                        hist, book, (char*)ws, status);
+  timer.before(stream);
+  codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, (char*)ws, status);
+  hipError_t e = hipGetLastError();
+  timer.after(stream);
+  return e;
 }
 
 }  // namespace hf

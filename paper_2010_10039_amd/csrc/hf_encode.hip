@@ -732,7 +732,11 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
   EncodeFn fn = pick(r, sym_bytes);
   const size_t lds = encode_lds_bytes(A, r);
   (void)blocks_per_cu(fn, lds);  // sets the LDS attribute when above 64 KiB
-  return launch_stamped(fn, dim3(nslabs), dim3(kEncThreads), lds, stream, timer.ev_before, timer.ev_after, a);
+  timer.before(stream);
+  hipLaunchKernelGGL(fn, dim3(nslabs), dim3(kEncThreads), lds, stream, a);
+  e = hipGetLastError();
+  timer.after(stream);
+  return e;
 }
 
 hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,
@@ -744,7 +748,7 @@ hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* 
 
 hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
-                               hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
+                               hipStream_t stream) {
   if (nitems == 0) return hipSuccess;
   const size_t T = (size_t)kEncThreads << r;
   const size_t lds = 4 * (T + 8 + (size_t)table_words(max_alphabet) + kEncThreads);
@@ -756,8 +760,8 @@ hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_i
     default: fn = batch_encode_kernel<4>; break;
   }
   if (lds > (64u << 10)) (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return launch_stamped(fn, dim3(nitems), dim3(kEncThreads), lds, stream, start, stop, d_streams, d_item_stream,
-                        d_items);
+  hipLaunchKernelGGL(fn, dim3(nitems), dim3(kEncThreads), lds, stream, d_streams, d_item_stream, d_items);
+  return hipGetLastError();
 }
 
 }  // namespace hf

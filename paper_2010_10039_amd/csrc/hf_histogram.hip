@@ -351,18 +351,19 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
     (void)hipFuncSetAttribute((const void*)histogram_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)histogram_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
-  if (A == 0) {
-    timer.before(stream);
-    timer.after(stream);
-  }
+  timer.before(stream);
   for (uint32_t lo = 0; lo < A; lo += W) {
     const uint32_t w = std::min(W, A - lo);
-    const hipEvent_t start = timer.start_if(lo == 0), stop = timer.stop_if(lo + w >= A);
-    e = launch_stamped(sym_bytes == 1 ? histogram_kernel<1> : histogram_kernel<2>, dim3((uint32_t)grid),
-                       dim3(kHistThreads), lds, stream, start, stop, sym, n, A, lo, w, R, nslabs, nblocks, hist,
-                       slab_hist, status);
+    if (sym_bytes == 1)
+      histogram_kernel<1><<<(uint32_t)grid, kHistThreads, lds, stream>>>(sym, n, A, lo, w, R, nslabs, nblocks, hist,
+                                                                         slab_hist, status);
+    else
+      histogram_kernel<2><<<(uint32_t)grid, kHistThreads, lds, stream>>>(sym, n, A, lo, w, R, nslabs, nblocks, hist,
+                                                                         slab_hist, status);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  timer.after(stream);
   if (slab_hist) {
     hist_reduce_kernel<<<(nslabs + kReduceRows - 1) / kReduceRows, kHistThreads, 0, stream>>>(slab_hist, nslabs, A,
                                                                                               hist);

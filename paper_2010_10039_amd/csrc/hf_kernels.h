@@ -1,11 +1,8 @@
 // hf_kernels.h -- host-side launchers of the libhf kernels (internal).
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-
-#include <tuple>
 
 #include "hf.h"
 
@@ -32,11 +29,7 @@ __host__ __device__ inline uint64_t slab_begin(uint64_t g, uint64_t nblocks, uin
   return s < n ? s : n;
 }
 
-// A pair of events to time one stage's main kernel(s) with, when armed.
-// launch() attaches them to the dispatch itself (the runtime stamps them
-// from the kernel's own start and end, with no extra stream packets);
-// before()/after() record them as separate packets where a stage launches
-// nothing.
+// Records a pair of events around one stage's main kernel(s) when armed.
 struct KernelTimer {
   hipEvent_t ev_before = nullptr;
   hipEvent_t ev_after = nullptr;
@@ -46,23 +39,7 @@ struct KernelTimer {
   void after(hipStream_t s) const {
     if (ev_after) (void)hipEventRecord(ev_after, s);
   }
-  hipEvent_t start_if(bool first) const { return first ? ev_before : nullptr; }
-  hipEvent_t stop_if(bool last) const { return last ? ev_after : nullptr; }
 };
-
-// kernel<<<grid, block, lds, stream>>>(args...), with `start` stamped when
-// the dispatch begins and `stop` when it ends (either may be null).
-template <typename... Params, typename... Args>
-hipError_t launch_stamped(void (*kernel)(Params...), dim3 grid, dim3 block, size_t lds, hipStream_t stream,
-                          hipEvent_t start, hipEvent_t stop, Args... args) {
-  std::tuple<Params...> vals{args...};
-  void* ptrs[sizeof...(Params) > 0 ? sizeof...(Params) : 1];
-  std::apply([&](auto&... v) {
-    int k = 0;
-    ((ptrs[k++] = (void*)&v), ...);
-  }, vals);
-  return hipExtLaunchKernel((const void*)kernel, grid, block, ptrs, lds, stream, start, stop, 0);
-}
 
 // Takes the one-shot timer armed by hf_time_next_main_kernel on this host
 // thread (empty if none).
@@ -139,7 +116,7 @@ hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* 
 // r in {3, 4, 5} (others run as 4); every item's alphabet is at most max_alphabet.
 hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
-                               hipStream_t stream, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+                               hipStream_t stream);
 
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
                                uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,

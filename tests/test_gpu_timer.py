@@ -1,5 +1,5 @@
-"""The stage timer (hf_time_next_main_kernel): the armed events are stamped
-by the timed stage's own kernel dispatch, within the bracketing step, and
+"""The stage timer (hf_time_next_main_kernel): the armed events are recorded
+around the timed stage's main kernel(s), within the bracketing step, and
 the outputs are unchanged by timing."""
 import numpy as np
 import pytest
@@ -22,7 +22,7 @@ def _events(k):
     return ev
 
 
-def test_stage_stamps_inside_the_step():
+def test_stage_timers_inside_the_step():
     x = W.gaussian_codes(n=(1 << 22) + 123, alphabet=1024)
     d = torch.from_numpy(x.view(np.int16)).cuda()
     enc = hf.Encoder(x.size, 1024, 4096, 4)
@@ -45,7 +45,7 @@ def test_stage_stamps_inside_the_step():
     assert torch.equal(enc.out, ref_out) and torch.equal(enc.offsets, ref_off)
 
 
-def test_batch_encode_stamps():
+def test_batch_encode_timer():
     syms, alph = W.batched_streams(12, seed=5, min_log2=14, max_log2=19, device="cuda")
     enc = hf.BatchEncoder(syms, alph, 4096, 0)
     enc.run()
