@@ -86,7 +86,7 @@ extern "C" {
 size_t hf_workspace_bytes(uint64_t n, uint32_t alphabet, uint32_t chunk_symbols) {
   (void)chunk_symbols;
   const uint64_t nblocks = (n + hf::kSlabBlock - 1) / hf::kSlabBlock;
-  const size_t enc = hf::encode_workspace_bytes((uint32_t)(nblocks > 0 ? nblocks : 1));
+  const size_t enc = hf::encode_workspace_bytes((uint32_t)(nblocks > 0 ? nblocks : 1), alphabet);
   const size_t cb = hf::codebook_workspace_bytes(alphabet);
   const size_t hist = (size_t)hf::histogram_internal_slabs(n, alphabet, num_cus()) * alphabet * 4;
   size_t need = enc > cb ? enc : cb;
@@ -174,7 +174,7 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
   if (d_slab_hist && (nslabs == 0 || book->alphabet > hf::kSlabHistMaxAlphabet)) return HF_ERR_ARG;
   if (n > 0 && nslabs == 0) nslabs = default_slabs(n, book->alphabet, sym_bytes);
   const uint32_t r = effective_r(reduce_log2);
-  if (n > 0 && (!d_ws || ws_bytes < hf::encode_workspace_bytes(nslabs) || ((uintptr_t)d_ws & 255)))
+  if (n > 0 && (!d_ws || ws_bytes < hf::encode_workspace_bytes(nslabs, book->alphabet) || ((uintptr_t)d_ws & 255)))
     return HF_ERR_WORKSPACE;
   return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, nslabs,
                                          d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,

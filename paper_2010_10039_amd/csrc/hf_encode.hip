@@ -49,6 +49,9 @@ constexpr int kPreWaves = kPreThreads / kWave;
 //                in LDS;
 //   kModeSplit : codes of 28 .. 31 bits, alphabet <= 4096: left-aligned
 //                codes and a byte table of 32 - cl in LDS;
+//   kModeGTable: codes <= 27 bits, alphabet above 8192: the table mode's
+//                packed entries in the workspace (read through L2), tile
+//                buffer in LDS;
 //   kModeGlobal: codes <= 32 bits: codebook read from global memory (L2),
 //                tile buffer in LDS;
 //   kModeWide  : longer codes: codebook from global memory and bits ORed
@@ -57,6 +60,7 @@ constexpr int kModeTable = 0;
 constexpr int kModeGlobal = 1;
 constexpr int kModeWide = 2;
 constexpr int kModeSplit = 3;
+constexpr int kModeGTable = 4;
 constexpr uint32_t kSplitMaxLen = 31;  // 32 - cl >= 1 keeps the word-completion test exact
 constexpr uint32_t kSplitMaxAlphabet = 4096;
 
@@ -99,6 +103,7 @@ struct EncArgs {
   uint64_t nchunks;
   uint32_t* status;
   uint32_t vec_ok;
+  const uint32_t* gtab;  // alphabets above 8192: packed entries [A + 1] in the workspace
 };
 
 template <int NS, int SB>
@@ -231,6 +236,7 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
                                             uint64_t expect) {
   constexpr uint32_t NS = 1u << R;
   constexpr uint32_t T = kEncThreads * NS;
+  constexpr bool kTabMode = MODE == kModeTable || MODE == kModeSplit || MODE == kModeGTable;
   const uint32_t tid = threadIdx.x;
   const uint64_t s_lo = slab_begin(g, a.nblocks, a.nslabs, a.n);
   const uint64_t s_hi = slab_begin(g + 1, a.nblocks, a.nslabs, a.n);
@@ -258,7 +264,7 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
     // ---- lookup: table entries (table modes) or symbols; lane bit count ----
     // ent: the code left-aligned (table mode: with 32 - cl in its low 5
     // bits); fsh: the split mode's 32 - cl (0: no code)
-    constexpr bool kTab = MODE == kModeTable || MODE == kModeSplit;
+    constexpr bool kTab = kTabMode;
     const uint8_t* tabf = (const uint8_t*)(tab + a.A + 1);
     uint32_t ent[NS];
     uint32_t fsh[MODE == kModeSplit ? NS : 1];
@@ -289,7 +295,7 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
 #pragma unroll
       for (uint32_t i = 0; i < NS; ++i) {
         const uint32_t sv = raw.symbol(i);
-        if (MODE == kModeTable) {
+        if (MODE == kModeTable || MODE == kModeGTable) {
           ent[i] = 0;
           if (i < nvalid) {
             const uint32_t e = tab[min(sv, a.A)];
@@ -459,12 +465,13 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       sh.tailw = 0;
     }
   }
-  if ((MODE == kModeTable || MODE == kModeSplit) && tid == 0 && run != expect)
+  if (kTabMode && tid == 0 && run != expect)
     raise_status(a.status, HF_ERR_SYMBOL);
 }
 
 __device__ __forceinline__ int encode_mode(uint32_t A, uint32_t lmax) {
   if (A <= kTableMaxAlphabet && lmax <= kPackedMaxLen) return kModeTable;
+  if (A > kTableMaxAlphabet && lmax <= kPackedMaxLen) return kModeGTable;
   if (A <= kSplitMaxAlphabet && lmax <= kSplitMaxLen) return kModeSplit;
   return lmax <= kLdsBufMaxLen ? kModeGlobal : kModeWide;
 }
@@ -518,6 +525,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   for (int w = 0; w < kEncWaves; ++w) G += sh.red[w];
   if (mode == kModeTable) encode_slab<R, SB, kModeTable>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
   else if (mode == kModeSplit) encode_slab<R, SB, kModeSplit>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
+  else if (mode == kModeGTable) encode_slab<R, SB, kModeGTable>(a, a.gtab, buf, dummy, sh, g, G, a.bits[g]);
   else if (mode == kModeGlobal) encode_slab<R, SB, kModeGlobal>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
 }
@@ -579,6 +587,7 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   a.info = bs.book.info;
   a.bits = nullptr;
   a.tails = nullptr;
+  a.gtab = nullptr;  // batched alphabets are at most 8192
   a.out = bs.out;
   a.cap_words = bs.cap_words;
   a.offsets = bs.offsets;
@@ -674,8 +683,19 @@ int encode_blocks_per_cu(uint32_t alphabet, uint32_t sym_bytes) {
   return blocks_per_cu(pick(r, sym_bytes), encode_lds_bytes(alphabet, r));
 }
 
-size_t encode_workspace_bytes(uint32_t nslabs) {
-  return align256((size_t)nslabs * 8) + align256((size_t)nslabs * 4);
+size_t encode_workspace_bytes(uint32_t nslabs, uint32_t alphabet) {
+  const size_t gtab = alphabet > kTableMaxAlphabet ? align256(((size_t)alphabet + 1) * 4) : 0;
+  return align256((size_t)nslabs * 8) + align256((size_t)nslabs * 4) + gtab;
+}
+
+// Packed table-mode entries of an alphabet above 8192, for the L2 table
+// mode (entries of codes over 27 bits stay 0; such books take another mode).
+__global__ __launch_bounds__(256) void gtable_kernel(const uint8_t* __restrict__ cl, const uint64_t* __restrict__ cw,
+                                                     uint32_t A, uint32_t* __restrict__ gtab) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s > A) return;
+  const uint32_t l = s < A ? cl[s] : 0u;
+  gtab[s] = (l && l <= kPackedMaxLen) ? pack_entry((uint32_t)cw[s], l) : 0u;
 }
 
 hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
@@ -729,6 +749,14 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
   a.nchunks = nchunks;
   a.status = status;
   a.vec_ok = ((uintptr_t)sym % 16) == 0 ? 1u : 0u;
+  a.gtab = nullptr;
+  if (A > kTableMaxAlphabet) {
+    uint32_t* gtab = (uint32_t*)((char*)ws + align256((size_t)nslabs * 8) + align256((size_t)nslabs * 4));
+    gtable_kernel<<<(A + 1 + 255) / 256, 256, 0, stream>>>(book.cl, book.cw, A, gtab);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.gtab = gtab;
+  }
   EncodeFn fn = pick(r, sym_bytes);
   const size_t lds = encode_lds_bytes(A, r);
   (void)blocks_per_cu(fn, lds);  // sets the LDS attribute when above 64 KiB

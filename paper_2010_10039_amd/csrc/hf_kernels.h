@@ -65,7 +65,7 @@ hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* 
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer);
 
 // Encoder workspace: per-slab bit totals and last-32-bit records.
-size_t encode_workspace_bytes(uint32_t nslabs);
+size_t encode_workspace_bytes(uint32_t nslabs, uint32_t alphabet);
 
 // Resident workgroups per CU of the default encoder for this alphabet.
 int encode_blocks_per_cu(uint32_t alphabet, uint32_t sym_bytes);

@@ -299,6 +299,8 @@ def _fib_stream(nfib: int, base: int, seed: int) -> np.ndarray:
                                               (30, 1024, 200, "split tables, 29-bit codes"),
                                               (32, 4096, 4000, "split tables, 31-bit codes"),
                                               (30, 8192, 5000, "codebook from global memory, 29-bit codes"),
+                                              (27, 32768, 20000, "L2 packed table, 26-bit codes"),
+                                              (30, 32768, 20000, "codebook from global memory, 29-bit codes"),
                                               (33, 1024, 200, "codebook from global memory, 32-bit codes"),
                                               (34, 1024, 200, "codes over 32 bits, bits ORed into the output")])
 def test_encode_long_codes(nfib, A, base, mode):
@@ -338,6 +340,18 @@ def test_encode_flags_symbol_without_code():
     book, _ = gpu_book(oracle.histogram(x, 1024))
     y = x.copy()
     y[12345] = 1000  # no code in this book
+    _, _, code = gpu_encode(y, book, 4096)
+    assert code == hf.HF_ERR_SYMBOL
+
+
+@pytest.mark.parametrize("A", [16384, 65536])
+def test_encode_l2_table_flags_symbol_without_code(A):
+    x = np.clip(np.rint(np.random.default_rng(8).normal(A / 2, A / 16, size=400_003)), 0, A - 1).astype(np.uint16)
+    book, _ = gpu_book(oracle.histogram(x, A))
+    assert int(book.info[1].item()) <= 27
+    y = x.copy()
+    y[123_457] = A - 1 if not np.any(x == A - 1) else 0  # no code in this book
+    assert not np.any(x == y[123_457])
     _, _, code = gpu_encode(y, book, 4096)
     assert code == hf.HF_ERR_SYMBOL
 
