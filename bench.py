@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--qps", type=float, default=0.0,
                    help="serve mode: a fixed mean arrival rate instead of the --rho points (0 = use --rho)")
     p.add_argument("--arena-gib", type=float, default=32.0, help="serve mode: HBM arena for outputs and state")
+    p.add_argument("--slots", type=int, default=8, help="serve mode: batches in flight (HIP streams)")
     p.add_argument("--streams", type=int, default=512, help="batch mode: streams per step")
     p.add_argument("--tuning", default=os.path.join(ROOT, "paper_2010_10039_amd", "tuning_mi355x.json"),
                    help="batch mode: autotuner table (tuned on the device when the file is missing)")
@@ -306,7 +307,7 @@ def run_serve(args):
     log(f"generated {len(trace)} requests, {total} bytes (mean {mean_bytes / 1e6:.1f} MB), "
         f"in {time.perf_counter() - t0:.1f}s")
     cap = int(args.arena_gib * (1 << 30))
-    servers = (("continuous_batching", dict(slots=3, max_batch=32)),
+    servers = (("continuous_batching", dict(slots=args.slots, max_batch=32)),
                ("plain_one_at_a_time", dict(slots=1, max_batch=1, use_batch=False)))
 
     def make(arrivals):

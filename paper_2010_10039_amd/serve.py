@@ -442,7 +442,7 @@ class GpuExecutor:
         return [int(vals[k]) for k in idx]
 
 
-def serve(requests: list, capacity: int, slots: int = 3, max_batch: int = 32, keep_results: bool = False,
+def serve(requests: list, capacity: int, slots: int = 8, max_batch: int = 32, keep_results: bool = False,
           device="cuda", use_batch: bool = True, solo_bytes: int = 32 << 20, max_batch_bytes: int = 64 << 20):
     """Serves `requests` (sorted by arrival, each with .sym on the device)
     in real time; returns the ServeLoop (finished requests with their
