@@ -32,8 +32,8 @@ def log(msg: str) -> None:
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="lorenzo3d_512cube_u16_A1024")
     p.add_argument("--chunk", type=int, default=4096)
     p.add_argument("--reduce-log2", type=int, default=0)
@@ -50,6 +50,9 @@ def parse():
                    help="serve mode: a fixed mean arrival rate instead of the --rho points (0 = use --rho)")
     p.add_argument("--arena-gib", type=float, default=32.0, help="serve mode: HBM arena for outputs and state")
     p.add_argument("--slots", type=int, default=8, help="serve mode: batches in flight (HIP streams)")
+    p.add_argument("--solo-mib", type=float, default=32.0,
+                   help="serve mode: requests of at least this many MiB run alone with plain calls")
+    p.add_argument("--batch-mib", type=float, default=64.0, help="serve mode: input bytes per batch, at most")
     p.add_argument("--streams", type=int, default=512, help="batch mode: streams per step")
     p.add_argument("--tuning", default=os.path.join(ROOT, "paper_2010_10039_amd", "tuning_mi355x.json"),
                    help="batch mode: autotuner table (tuned on the device when the file is missing)")
@@ -307,7 +310,8 @@ def run_serve(args):
     log(f"generated {len(trace)} requests, {total} bytes (mean {mean_bytes / 1e6:.1f} MB), "
         f"in {time.perf_counter() - t0:.1f}s")
     cap = int(args.arena_gib * (1 << 30))
-    servers = (("continuous_batching", dict(slots=args.slots, max_batch=32)),
+    servers = (("continuous_batching", dict(slots=args.slots, max_batch=32, solo_bytes=int(args.solo_mib * 2**20),
+                                            max_batch_bytes=int(args.batch_mib * 2**20))),
                ("plain_one_at_a_time", dict(slots=1, max_batch=1, use_batch=False)))
 
     def make(arrivals):
@@ -465,6 +469,15 @@ def main():
     for s in ev_other:
         stage_ms[s] = sum(a.elapsed_time(b) for a, b in ev_other[s]) / args.steps
     stages = ("hist", "codebook", "encode")
+    # median over separately bracketed steps (an event pair around each)
+    nmed = max(21, min(args.steps, 101))
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nmed)]
+    for a, b in pairs:
+        a.record()
+        enc.run(d)
+        b.record()
+    torch.cuda.synchronize()
+    median_us = float(np.median([a.elapsed_time(b) for a, b in pairs])) * 1e3
     value = n * sb / (ms_per_step * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step (wall {wall * 1e6 / args.steps:.1f} us); "
         + ", ".join(f"{s} {stage_ms[s] * 1e3:.1f} us" for s in stages))
@@ -527,6 +540,8 @@ def main():
             "input_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 4),
             "e2e_algorithmic_frac_of_hbm_peak": round(e2e_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "stage_us": {s: round(stage_ms[s] * 1e3, 2) for s in stages},
+            "median_step_us": round(median_us, 2),
+            "median_steps": nmed,
             "device_copy_gbs": round(copy_gbs, 1),
         },
         "roofline": roofline,
