@@ -6,7 +6,7 @@
  * The paper splits encoding into four stages (Sec. 4): histogramming,
  * codebook construction, canonization, and encoding with bit
  * concatenation.  hf_histogram is stage 1, hf_build_codebook is stages 2+3,
- * hf_encode is stage 4; hf_decode_check re-reads the stream with the
+ * hf_encode is stage 4; hf_decode inverts it, and hf_decode_check re-reads the stream with the
  * canonical decode tables and compares it with the input.
  *
  * Conventions shared by every entry point:
@@ -45,7 +45,8 @@ typedef enum {
   HF_ERR_CAPACITY = 17,  /* encoded stream longer than the output buffer (device) */
   HF_ERR_CODELEN = 18,   /* a code longer than 64 bits (device; unreachable for n < 2^32) */
   HF_ERR_MISMATCH = 19,  /* hf_decode_check found a difference (device) */
-  HF_ERR_INTERNAL = 20   /* a bounded wait or loop hit its limit (device; a bug guard) */
+  HF_ERR_INTERNAL = 20,  /* a bounded wait or loop hit its limit (device; a bug guard) */
+  HF_ERR_STREAM = 21     /* hf_decode: a chunk does not decode with the codebook (device) */
 } hf_status;
 
 #define HF_MAX_CODELEN 64
@@ -162,6 +163,25 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
                     const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,
                     uint64_t* d_chunk_bit_offsets, void* d_ws, size_t ws_bytes,
                     uint32_t* d_status, void* stream);
+
+/*
+ * Decoder (the inverse path; the paper scopes decoding out, Sec. 1, and
+ * gives its tables in Sec. 4.2.2 and Table 1): writes the n symbols encoded
+ * in d_in (a stream from hf_encode with its chunk offsets, chunk_symbols as
+ * used there, and the same codebook) to d_sym_out (n * sym_bytes bytes).
+ * Chunks are decoded in parallel, each from its offset, by treeless
+ * canonical decoding: the first l bits v form a code of length l when
+ * First[l] <= v < First[l] + (Entry[l + 1] - Entry[l]); its symbol is
+ * rev[Entry[l] + v - First[l]].  Codes of up to 12 bits are resolved with
+ * one lookup in a table of all 12-bit prefixes, built in d_ws
+ * (hf_decode_workspace_bytes(), 16 KiB, 256-byte aligned).  A chunk that
+ * meets a bit pattern that is no code, or ends off its next offset, raises
+ * HF_ERR_STREAM (its symbols are then unspecified).
+ */
+size_t hf_decode_workspace_bytes(void);
+hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, uint64_t n,
+                    uint32_t sym_bytes, uint32_t chunk_symbols, const hf_codebook* book, void* d_sym_out,
+                    void* d_ws, size_t ws_bytes, uint32_t* d_status, void* stream);
 
 /*
  * Checker: decodes every chunk of d_out from its offset with the canonical

@@ -124,6 +124,7 @@ const char* hf_status_string(uint32_t code) {
     case HF_ERR_CODELEN: return "code length above 64 bits";
     case HF_ERR_MISMATCH: return "decoded stream differs from the input";
     case HF_ERR_INTERNAL: return "internal bound exceeded";
+    case HF_ERR_STREAM: return "stream does not decode with the codebook";
     default: return "unknown status";
   }
 }
@@ -179,6 +180,24 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
   return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, nslabs,
                                          d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,
                                          d_ws, d_status, (hipStream_t)stream, timer));
+}
+
+size_t hf_decode_workspace_bytes(void) { return hf::decode_workspace_bytes(); }
+
+hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, uint64_t n, uint32_t sym_bytes,
+                    uint32_t chunk_symbols, const hf_codebook* book, void* d_sym_out, void* d_ws,
+                    size_t ws_bytes, uint32_t* d_status, void* stream) {
+  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
+      !d_chunk_bit_offsets || !d_status || (n > 0 && (!d_in || !d_sym_out)))
+    return HF_ERR_ARG;
+  if (n > 0 && (!d_ws || ws_bytes < hf::decode_workspace_bytes() || ((uintptr_t)d_ws & 255)))
+    return HF_ERR_WORKSPACE;
+  hf::KernelTimer timer = hf::take_main_timer();
+  timer.before((hipStream_t)stream);
+  const hipError_t e = hf::launch_decode(d_in, d_chunk_bit_offsets, n, sym_bytes, log2u(chunk_symbols), *book,
+                                         d_sym_out, d_ws, d_status, (hipStream_t)stream);
+  timer.after((hipStream_t)stream);
+  return launch_result(e);
 }
 
 hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets, uint64_t n,

@@ -118,6 +118,13 @@ hipError_t launch_batch_encode(const BatchStream* d_streams, const uint32_t* d_i
                                const uint32_t* d_items, uint32_t nitems, uint32_t r, uint32_t max_alphabet,
                                hipStream_t stream);
 
+// Decoder workspace: the prefix table.
+size_t decode_workspace_bytes();
+
+hipError_t launch_decode(const uint32_t* words, const uint64_t* offsets, uint64_t n, uint32_t sym_bytes,
+                         uint32_t chunk_log2, const hf_codebook& book, void* out, void* ws, uint32_t* status,
+                         hipStream_t stream);
+
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
                                uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,
                                const void* expected, uint64_t* result, uint32_t* status,

@@ -25,6 +25,7 @@ HF_ERR_CAPACITY = 17
 HF_ERR_CODELEN = 18
 HF_ERR_MISMATCH = 19
 HF_ERR_INTERNAL = 20
+HF_ERR_STREAM = 21
 MAX_CODELEN = 64
 
 if not os.path.exists(_LIB_PATH):
@@ -74,6 +75,10 @@ _lib.hf_encode.restype = ctypes.c_int
 _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
                                  _SZ, _P, _P]
 _lib.hf_decode_check.restype = ctypes.c_int
+_lib.hf_decode_workspace_bytes.argtypes = []
+_lib.hf_decode_workspace_bytes.restype = _SZ
+_lib.hf_decode.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _SZ, _P, _P]
+_lib.hf_decode.restype = ctypes.c_int
 
 
 class HFError(RuntimeError):
@@ -260,6 +265,30 @@ def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor,
                                 _ptr(sym), _ptr(result), _ptr(ws), 0 if ws is None else ws.numel(),
                                 _ptr(status), _stream()), "hf_decode_check")
     return result
+
+
+def hf_decode_workspace_bytes() -> int:
+    return int(_lib.hf_decode_workspace_bytes())
+
+
+def hf_decode(words: torch.Tensor, offsets: torch.Tensor, n: int, dtype: torch.dtype, chunk_symbols: int,
+              book: Codebook, out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+              status: torch.Tensor | None = None) -> torch.Tensor:
+    """Decodes n symbols (dtype torch.uint8 or torch.int16 holding uint16)
+    from a stream and its chunk offsets; returns `out`."""
+    if dtype not in (torch.uint8, torch.int16):
+        raise TypeError(f"symbols must be uint8 or int16 (holding uint16), got {dtype}")
+    sb = 1 if dtype == torch.uint8 else 2
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=words.device)
+    if ws is None:
+        ws = torch.empty(hf_decode_workspace_bytes(), dtype=torch.uint8, device=words.device)
+    if status is None:
+        status = new_status(words.device)
+    s = book.struct()
+    _check(_lib.hf_decode(_ptr(words), _ptr(offsets), n, sb, chunk_symbols, ctypes.byref(s), _ptr(out), _ptr(ws),
+                          ws.numel(), _ptr(status), _stream()), "hf_decode")
+    return out
 
 
 class Encoder:

@@ -28,8 +28,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared_functions()
-    for want in ("hf_histogram", "hf_build_codebook", "hf_encode", "hf_decode_check",
-                 "hf_workspace_bytes", "hf_bound_words"):
+    for want in ("hf_histogram", "hf_build_codebook", "hf_encode", "hf_decode", "hf_decode_check",
+                 "hf_workspace_bytes", "hf_decode_workspace_bytes", "hf_bound_words"):
         assert want in names
 
 
@@ -87,6 +87,34 @@ def test_host_argument_checks_return_before_device_work(lib):
     assert lib.hf_histogram(d, 10_000, 2, 8192, d, 2, d, None, 0, d, None) == 1
     lib.hf_status_string.restype = ctypes.c_char_p
     assert b"argument" in lib.hf_status_string(1)
+
+
+class _Book(ctypes.Structure):
+    _fields_ = [("alphabet", ctypes.c_uint32)] + [(k, ctypes.c_void_p) for k in ("cl", "cw", "first", "entry", "rev",
+                                                                                 "info")]
+
+
+def test_decoder_argument_checks(lib):
+    P = ctypes.c_void_p
+    U32, U64, SZ = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    lib.hf_decode.argtypes = [P, P, U64, U32, U32, ctypes.POINTER(_Book), P, P, SZ, P, P]
+    lib.hf_decode_workspace_bytes.restype = SZ
+    need = lib.hf_decode_workspace_bytes()
+    assert need == 4 << 12
+    d, ws = P(0x1000), P(0x100000)
+    book = _Book(1024, *([0x2000] * 6))
+    # chunk not a power of two / out of range, bad width, missing buffers
+    assert lib.hf_decode(d, d, 100, 2, 1000, ctypes.byref(book), d, ws, need, d, None) == 1
+    assert lib.hf_decode(d, d, 100, 2, 128, ctypes.byref(book), d, ws, need, d, None) == 1
+    assert lib.hf_decode(d, d, 100, 3, 4096, ctypes.byref(book), d, ws, need, d, None) == 1
+    assert lib.hf_decode(d, d, 100, 2, 4096, ctypes.byref(book), None, ws, need, d, None) == 1
+    assert lib.hf_decode(d, None, 100, 2, 4096, ctypes.byref(book), d, ws, need, d, None) == 1
+    # workspace missing, too small, misaligned
+    assert lib.hf_decode(d, d, 100, 2, 4096, ctypes.byref(book), d, None, need, d, None) == 2
+    assert lib.hf_decode(d, d, 100, 2, 4096, ctypes.byref(book), d, ws, need - 1, d, None) == 2
+    assert lib.hf_decode(d, d, 100, 2, 4096, ctypes.byref(book), d, P(0x100004), need, d, None) == 2
+    lib.hf_status_string.restype = ctypes.c_char_p
+    assert b"decode" in lib.hf_status_string(21)
 
 
 def test_slab_count_bounds(lib):
