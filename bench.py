@@ -39,10 +39,11 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
-    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve"), default="pipeline",
+    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode"), default="pipeline",
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
-                        "serve: a Poisson trace of requests, continuous batching vs one request at a time")
+                        "serve: a Poisson trace of requests, continuous batching vs one request at a time; "
+                        "decode: hf_decode of the workload's encoded stream")
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     p.add_argument("--rho", default="0.5,0.8",
                    help="serve mode: offered loads as fractions of the measured saturated capacity")
@@ -381,6 +382,110 @@ def run_serve(args):
     }
 
 
+def run_decode(args):
+    """Decoding (the inverse path): the workload is encoded once, then each
+    step is one hf_decode of the whole stream into HBM.  The value is GB/s
+    of decoded symbols.  The roofline's algorithmic bytes are the stream
+    and offsets read plus the symbols written.  The CPU baseline is the
+    oracle's serial decoder on the first chunks of the same stream."""
+    import torch
+
+    import oracle
+    from paper_2010_10039_amd import hf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    spec = workloads.WORKLOADS[args.workload]
+    A = spec["alphabet"]
+    x = workloads.make(args.workload)
+    sb = x.dtype.itemsize
+    dt = torch.int16 if sb == 2 else torch.uint8
+    d = torch.from_numpy(x.view(np.int16) if sb == 2 else x).cuda()
+    n = x.size
+    enc = hf.Encoder(n, A, args.chunk, args.reduce_log2)
+    enc.run(d)
+    torch.cuda.synchronize()
+    hf.raise_on_status(enc.status, "encode")
+    total_bits = int(enc.offsets[-1].item())
+    nwords = (total_bits + 31) // 32
+    out = torch.empty(n, dtype=dt, device="cuda")
+    ws = torch.empty(hf.hf_decode_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    status = hf.new_status()
+
+    def step(timer=None):
+        if timer is not None:
+            hf.hf_time_next_main_kernel(*timer)
+        hf.hf_decode(enc.out, enc.offsets, n, dt, args.chunk, enc.book, out=out, ws=ws, status=status)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record()
+        b.record()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        step(ev[k])
+    stop.record()
+    torch.cuda.synchronize()
+    hf.raise_on_status(status, "decode")
+    if not torch.equal(out, d):
+        raise SystemExit("decoded symbols differ from the input")
+    ms = start.elapsed_time(stop) / args.steps
+    launch_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    nch = (n + args.chunk - 1) // args.chunk
+    alg_bytes = nwords * 4 + (nch + 1) * 8 + n * sb
+    value = n * sb / (ms * 1e-3) / 1e9
+    log(f"decode: {ms * 1e3:.1f} us/step, {value:.1f} GB/s of symbols; decoder launches {launch_ms * 1e3:.1f} us")
+    cpu = None
+    if args.cpu_seconds > 0:
+        ref = oracle.Codebook(enc.book.cl.cpu().numpy(), enc.book.cw.cpu().numpy().view(np.uint64),
+                              enc.book.first.cpu().numpy().view(np.uint64),
+                              enc.book.entry.cpu().numpy().view(np.uint32),
+                              enc.book.rev.cpu().numpy().view(np.uint32),
+                              enc.book.info.cpu().numpy().view(np.uint64))
+        words = enc.out[:nwords].cpu().numpy().view(np.uint32)
+        offs = enc.offsets.cpu().numpy().view(np.uint64)
+        k = 1
+        t0 = time.perf_counter()
+        while True:  # whole chunks from the start until the time budget is spent
+            cnt = min(n, k * args.chunk)
+            got, _ = oracle.decode(words, int(offs[min(nch, k)]), cnt, ref, dtype=x.dtype)
+            if time.perf_counter() - t0 > args.cpu_seconds / 4 or cnt == n:
+                break
+            k *= 2
+        t0 = time.perf_counter()
+        got, _ = oracle.decode(words, int(offs[min(nch, k)]), cnt, ref, dtype=x.dtype)
+        dt_cpu = time.perf_counter() - t0
+        assert np.array_equal(got, x[:cnt])
+        cpu = {"value": round(cnt * sb / dt_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"serial decode of the first {cnt} symbols ({min(nch, k)} chunks), {dt_cpu:.2f} s"}
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    return {
+        "metric": "decode GB/s of output symbols",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16" if sb == 2 else "u8",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_symbols": n, "alphabet": A, "chunk_symbols": args.chunk,
+                   "total_bits": total_bits, "chunks": nch},
+        "roofline": {"bound": "hbm", "kernel": "decode_kernel", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": alg_bytes, "avg_launch_us": round(launch_ms * 1e3, 2)},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -392,6 +497,9 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.mode == "decode":
+        print(json.dumps(run_decode(args)), flush=True)
         return
 
     import torch

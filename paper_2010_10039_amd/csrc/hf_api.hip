@@ -192,12 +192,8 @@ hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, u
     return HF_ERR_ARG;
   if (n > 0 && (!d_ws || ws_bytes < hf::decode_workspace_bytes() || ((uintptr_t)d_ws & 255)))
     return HF_ERR_WORKSPACE;
-  hf::KernelTimer timer = hf::take_main_timer();
-  timer.before((hipStream_t)stream);
-  const hipError_t e = hf::launch_decode(d_in, d_chunk_bit_offsets, n, sym_bytes, log2u(chunk_symbols), *book,
-                                         d_sym_out, d_ws, d_status, (hipStream_t)stream);
-  timer.after((hipStream_t)stream);
-  return launch_result(e);
+  return launch_result(hf::launch_decode(d_in, d_chunk_bit_offsets, n, sym_bytes, log2u(chunk_symbols), *book,
+                                         d_sym_out, d_ws, d_status, (hipStream_t)stream, hf::take_main_timer()));
 }
 
 hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets, uint64_t n,

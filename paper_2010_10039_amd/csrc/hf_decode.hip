@@ -139,43 +139,85 @@ __global__ __launch_bounds__(kDecLanes) void decode_kernel(
   const uint64_t stop = offsets[k + 1];
   const uint64_t i0 = k << chunk_log2;
   const uint64_t i1 = min(n, i0 + (1ull << chunk_log2));
-  // 64-bit window: words wi and wi + 1, the next bit at offset sh in it
-  uint64_t wi = offsets[k] >> 5;
+  // Window: two 4-word blocks in registers, cur (words wb .. wb + 3) and nxt
+  // (the next four, loaded when cur was entered, so a refill waits on a
+  // load issued some twenty symbols earlier); the next bit is bit sh of
+  // word wb + idx, idx < 4.
+  auto load = [&](uint64_t j) -> uint32_t { return j < nwords ? words[j] : 0u; };
+  uint64_t wb = (offsets[k] >> 5) & ~3ull;
+  uint32_t idx = (uint32_t)((offsets[k] >> 5) & 3);
   uint32_t sh = (uint32_t)(offsets[k] & 31);
-  uint32_t w0 = wi < nwords ? words[wi] : 0u;
-  uint32_t w1 = wi + 1 < nwords ? words[wi + 1] : 0u;
+  uint32_t c0 = load(wb), c1 = load(wb + 1), c2 = load(wb + 2), c3 = load(wb + 3);
+  uint32_t n0 = load(wb + 4), n1 = load(wb + 5), n2 = load(wb + 6), n3 = load(wb + 7);
   bool bad = false;
-  for (uint64_t i = i0; i < i1; ++i) {
-    const uint64_t win = ((((uint64_t)w0) << 32) | w1) << sh;  // at least 33 valid bits on top
-    const uint32_t t = tab[(uint32_t)(win >> (64 - kDecPeek))];
-    uint32_t len = t >> 16, sym = t & 0xFFFFu;
-    if (len == 0) {
-      // a code over kDecPeek bits (or none): lengthen bit by bit from memory
-      uint64_t q = wi * 32 + sh;
-      uint64_t v = 0;
-      uint32_t l = 0;
-      do {
-        v = 2 * v + (q < nwords * 32 ? (words[q >> 5] >> (31 - (q & 31))) & 1u : 0u);
-        ++q;
-        ++l;
-      } while (l < lmax && v < s_first[l]);
-      if (l == 0 || v < s_first[l] || v - s_first[l] >= (uint64_t)(s_entry[l + 1] - s_entry[l])) {
-        bad = true;
-        break;
+  // Symbols go out 16 bytes at a time (G per group; a chunk starts at a
+  // multiple of 256 symbols) when the output is 16-byte aligned, the ragged
+  // end of a chunk one by one.
+  constexpr uint32_t G = 16 / SB;
+  const bool vec = ((uintptr_t)out & 15) == 0;
+  uint32_t packed[4];
+  uint64_t i = i0;
+  while (i < i1 && !bad) {
+    const uint32_t cnt = i1 - i >= G ? G : (uint32_t)(i1 - i);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) packed[q] = 0;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+      if (g < cnt && !bad) {
+        const uint32_t w0 = idx == 0 ? c0 : idx == 1 ? c1 : idx == 2 ? c2 : c3;
+        const uint32_t w1 = idx == 0 ? c1 : idx == 1 ? c2 : idx == 2 ? c3 : n0;
+        const uint64_t win = ((((uint64_t)w0) << 32) | w1) << sh;  // at least 33 valid bits on top
+        const uint32_t t = tab[(uint32_t)(win >> (64 - kDecPeek))];
+        uint32_t len = t >> 16, sym = t & 0xFFFFu;
+        if (len == 0) {
+          // a code over kDecPeek bits (or none): lengthen over the next 64 bits
+          const uint32_t w2 = idx == 0 ? c2 : idx == 1 ? c3 : idx == 2 ? n0 : n1;
+          const uint64_t w64 = win | (sh ? (uint64_t)w2 >> (32 - sh) : 0ull);
+          uint64_t v = 0;
+          uint32_t l = 0;
+          do {
+            v = 2 * v + ((w64 >> (63 - l)) & 1u);
+            ++l;
+          } while (l < lmax && v < s_first[l]);
+          if (v < s_first[l] || v - s_first[l] >= (uint64_t)(s_entry[l + 1] - s_entry[l])) {
+            bad = true;
+            len = 0;
+          } else {
+            sym = rev[s_entry[l] + (uint32_t)(v - s_first[l])];
+            len = l;
+          }
+        }
+        packed[(g * SB) / 4] |= sym << (8 * ((g * SB) % 4));
+        sh += len;
+        while (sh >= 32) {
+          sh -= 32;
+          if (++idx == 4) {
+            idx = 0;
+            c0 = n0;
+            c1 = n1;
+            c2 = n2;
+            c3 = n3;
+            wb += 4;
+            n0 = load(wb + 4);
+            n1 = load(wb + 5);
+            n2 = load(wb + 6);
+            n3 = load(wb + 7);
+          }
+        }
       }
-      sym = rev[s_entry[l] + (uint32_t)(v - s_first[l])];
-      len = l;
     }
-    if (SB == 1) ((uint8_t*)out)[i] = (uint8_t)sym;
-    else ((uint16_t*)out)[i] = (uint16_t)sym;
-    sh += len;
-    while (sh >= 32) {
-      w0 = w1;
-      ++wi;
-      w1 = wi + 1 < nwords ? words[wi + 1] : 0u;
-      sh -= 32;
+    if (vec && cnt == G && !bad) {
+      *(uint4*)((char*)out + i * SB) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    } else {
+      for (uint32_t g = 0; g < cnt; ++g) {
+        const uint32_t sym = (packed[(g * SB) / 4] >> (8 * ((g * SB) % 4))) & (SB == 1 ? 0xFFu : 0xFFFFu);
+        if (SB == 1) ((uint8_t*)out)[i + g] = (uint8_t)sym;
+        else ((uint16_t*)out)[i + g] = (uint16_t)sym;
+      }
     }
+    i += cnt;
   }
+  const uint64_t wi = wb + idx;
   if (bad || wi * 32 + sh != stop) raise_status(status, HF_ERR_STREAM);
 }
 
@@ -185,21 +227,28 @@ size_t decode_workspace_bytes() { return (size_t)4 << kDecPeek; }
 
 hipError_t launch_decode(const uint32_t* words, const uint64_t* offsets, uint64_t n, uint32_t sym_bytes,
                          uint32_t chunk_log2, const hf_codebook& book, void* out, void* ws, uint32_t* status,
-                         hipStream_t stream) {
-  if (n == 0) return hipSuccess;
+                         hipStream_t stream, const KernelTimer& timer) {
+  if (n == 0) {
+    timer.before(stream);
+    timer.after(stream);
+    return hipSuccess;
+  }
   uint32_t* tab = (uint32_t*)ws;
   decode_table_kernel<<<(1u << kDecPeek) / 256, 256, 0, stream>>>(book.first, book.entry, book.rev, book.info, tab);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
   const uint32_t grid = (uint32_t)((nchunks + kDecLanes - 1) / kDecLanes);
+  timer.before(stream);
   if (sym_bytes == 1)
     decode_kernel<1><<<grid, kDecLanes, 0, stream>>>(words, offsets, n, chunk_log2, nchunks, tab, book.first,
                                                      book.entry, book.rev, book.info, out, status);
   else
     decode_kernel<2><<<grid, kDecLanes, 0, stream>>>(words, offsets, n, chunk_log2, nchunks, tab, book.first,
                                                      book.entry, book.rev, book.info, out, status);
-  return hipGetLastError();
+  e = hipGetLastError();
+  timer.after(stream);
+  return e;
 }
 
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,

@@ -105,6 +105,21 @@ def test_decode_large_alphabet():
     check(x, 65536, 1024)
 
 
+@pytest.mark.parametrize("shift", [1, 3])  # output 2 or 6 bytes past a 16-byte boundary: element stores
+def test_decode_unaligned_output(shift):
+    x = W.gaussian_codes(n=100_000, seed=12)
+    ref = oracle.codebook(oracle.histogram(x, 1024))
+    words, offs, tb = oracle.encode(x, ref, 1024)
+    buf = torch.zeros(x.size + 8, dtype=torch.int16, device="cuda")
+    status = hf.new_status()
+    hf.hf_decode(_t(words, np.int32), _t(offs.astype(np.uint64), np.int64), x.size, torch.int16, 1024,
+                 dev_book(ref, 1024), out=buf[shift:shift + x.size], status=status)
+    assert hf.read_status(status) == 0
+    got = buf.cpu().numpy().view(np.uint16)
+    assert np.array_equal(got[shift:shift + x.size], x)
+    assert np.all(got[:shift] == 0) and np.all(got[shift + x.size:] == 0)
+
+
 def test_decode_gpu_encoder_round_trip():
     x = W.gaussian_codes(n=3_000_017, seed=11)
     enc = hf.Encoder(x.size, 1024, 4096, 0)
