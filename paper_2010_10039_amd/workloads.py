@@ -67,18 +67,11 @@ def _smooth_field(dim: int, rng: np.random.Generator, nwaves: int = 8):
     return f
 
 
-def lorenzo_quant_codes(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01,
-                        eb_rel: float = 1e-4, radius: int = 512) -> np.ndarray:
-    """Error-bounded quantization codes of a smooth 3D field (SZ-style).
-
-    The stand-in for the paper's Nyx-Quant input (Sec. 5.1.3): a dim^3 float32
-    field made of 8 random sinusoids plus Gaussian noise of standard deviation
-    noise_rel_std * std(field); absolute error bound eb = eb_rel * value range.
-    Each value is prequantized to d = rint(x / (2 eb)); the 3D Lorenzo
-    predictor's residual (the mixed first difference along i, j, k with zero
-    padding outside the grid) is offset by `radius`; codes outside
-    [1, 2*radius - 1] become 0, SZ's outlier marker.  Returns uint16 codes in
-    C order, alphabet 2*radius."""
+def lorenzo_field(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01, eb_rel: float = 1e-4):
+    """A dim^3 float32 field and its absolute error bound (the Nyx-like
+    input of Sec. 5.1.3): 8 random sinusoids plus Gaussian noise of standard
+    deviation noise_rel_std * std(field); eb = eb_rel * value range.
+    Returns (x as a C-order numpy float32 array of shape (dim, dim, dim), eb)."""
     import torch
 
     rng = np.random.default_rng(seed)
@@ -91,8 +84,26 @@ def lorenzo_quant_codes(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.
     x.add_(noise, alpha=noise_rel_std * sd)
     del noise
     eb = eb_rel * float(x.max() - x.min())
+    return x.numpy(), eb
+
+
+def lorenzo_quant_codes(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01,
+                        eb_rel: float = 1e-4, radius: int = 512) -> np.ndarray:
+    """Error-bounded quantization codes of a smooth 3D field (SZ-style).
+
+    The stand-in for the paper's Nyx-Quant input (Sec. 5.1.3), made from
+    lorenzo_field(dim, seed).  Each value is prequantized to
+    d = rint(x / (2 eb)) in float64; the 3D Lorenzo
+    predictor's residual (the mixed first difference along i, j, k with zero
+    padding outside the grid) is offset by `radius`; codes outside
+    [1, 2*radius - 1] become 0, SZ's outlier marker.  Returns uint16 codes in
+    C order, alphabet 2*radius."""
+    import torch
+
+    xn, eb = lorenzo_field(dim, seed, noise_rel_std, eb_rel)
+    x = torch.from_numpy(xn)
     d = torch.round(x.to(torch.float64) / (2.0 * eb)).to(torch.int32)
-    del x
+    del x, xn
     for axis in range(3):
         e = d.clone()
         sl_hi = [slice(None)] * 3
