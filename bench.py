@@ -39,11 +39,14 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
-    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode"), default="pipeline",
+    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend"),
+                   default="pipeline",
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
                         "serve: a Poisson trace of requests, continuous batching vs one request at a time; "
-                        "decode: hf_decode of the workload's encoded stream")
+                        "decode: hf_decode of the workload's encoded stream; "
+                        "frontend: from the 512^3 float field, fused quantization + Lorenzo + histogram, "
+                        "then codebook and encode")
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     p.add_argument("--rho", default="0.5,0.8",
                    help="serve mode: offered loads as fractions of the measured saturated capacity")
@@ -64,18 +67,22 @@ KERNEL_SOURCES = ["paper_2010_10039_amd/csrc/hf_encode.hip", "paper_2010_10039_a
                   "paper_2010_10039_amd/csrc/hf_kernels.h"]
 
 
-def measured_traffic(kernel: str, profile: str):
+FRONTEND_SOURCES = ["paper_2010_10039_amd/csrc/hf_lorenzo.hip", "paper_2010_10039_amd/csrc/hf_device.h",
+                    "paper_2010_10039_amd/csrc/hf_kernels.h"]
+
+
+def measured_traffic(kernel: str, profile: str, sources=None):
     """HBM bytes per dispatch of `kernel` from a committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a device copy), or
     None when the summary is missing or the kernel's sources changed since
-    the counters were taken (sha256 over KERNEL_SOURCES)."""
+    the counters were taken (sha256 over `sources`, KERNEL_SOURCES by default)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for src in KERNEL_SOURCES:
+    for src in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     for line in open(path):
@@ -486,6 +493,133 @@ def run_decode(args):
     }
 
 
+def run_frontend(args):
+    """The quantizing front end ahead of the encoder: the 512^3 float32 field
+    (the Nyx-like input) is resident; one step is hf_lorenzo_histogram (codes,
+    histogram and per-slab counts in one pass) -> hf_build_codebook ->
+    hf_encode.  The value is GB/s of field bytes.  The roofline's algorithmic
+    bytes are the field read once plus the codes and per-slab counts
+    written.  The CPU baseline is the oracle (numpy front end, then the C
+    histogram, codebook and encoder) on the first planes of the same field."""
+    import torch
+
+    import oracle
+    from oracle import lorenzo as lz
+    from paper_2010_10039_amd import hf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dim, radius, chunk = 512, 512, args.chunk
+    A = 2 * radius
+    t0 = time.perf_counter()
+    x, eb = workloads.lorenzo_field(dim, seed=0)
+    inv = float(np.float32(1.0 / (2.0 * eb)))
+    n = x.size
+    log(f"generated the {dim}^3 field in {time.perf_counter() - t0:.1f}s, eb={eb:.6g}")
+    xd = torch.from_numpy(x.reshape(-1)).cuda()
+    S = hf.hf_slab_count(n, A)
+    codes = torch.empty(n, dtype=torch.int16, device="cuda")
+    hist = torch.empty(A, dtype=torch.int32, device="cuda")
+    sh = torch.empty(S * A, dtype=torch.int32, device="cuda")
+    book = hf.Codebook.empty(A)
+    ws = hf.new_workspace(n, A, chunk)
+    status = hf.new_status()
+    out = torch.empty(hf.hf_bound_words(n, A), dtype=torch.int32, device="cuda")
+    offs = torch.empty((n + chunk - 1) // chunk + 1, dtype=torch.int64, device="cuda")
+
+    def step(timer=None):
+        if timer is not None:
+            hf.hf_time_next_main_kernel(*timer)
+        hf.hf_lorenzo_histogram(xd, (dim, dim, dim), inv, radius, codes, hist, S, sh)
+        hf.hf_build_codebook(hist, book, ws, status)
+        hf.hf_encode(codes, book, chunk, args.reduce_log2, out, offs, ws, status, S, sh)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hf.raise_on_status(status, "warmup")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record()
+        b.record()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        step(ev[k])
+    stop.record()
+    torch.cuda.synchronize()
+    hf.raise_on_status(status, "timed steps")
+    ms = start.elapsed_time(stop) / args.steps
+    launch_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    nmed = max(21, min(args.steps, 101))
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nmed)]
+    for a, b in pairs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    median_us = float(np.median([a.elapsed_time(b) for a, b in pairs])) * 1e3
+    info = book.info.cpu().numpy().view(np.uint64)
+    total_bits = int(info[2])
+    # checks (untimed): plane windows of the codes against the oracle, and the stream against the codes
+    got = codes.cpu().numpy().view(np.uint16).reshape(dim, dim, dim)
+    for z in (0, dim // 2, dim - 3):
+        lo = max(z - 1, 0)
+        want = lz.lorenzo_codes(x[lo:z + 3], inv, radius).reshape(-1, dim, dim)[z - lo:]
+        if not np.array_equal(got[z:z + 3], want):
+            raise SystemExit(f"front-end codes differ from the oracle in planes {z}..{z + 2}")
+    res = hf.hf_decode_check(out, offs, codes, chunk, book)
+    torch.cuda.synchronize()
+    if int(res[0].item()) != 0:
+        raise SystemExit("decode check of the encoded codes failed")
+    value = n * 4 / (ms * 1e-3) / 1e9
+    alg_bytes = n * 4 + n * 2 + S * A * 4
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic("lorenzo_hist_kernel", "lorenzo_hist_lorenzo512_hbm_traffic.txt", FRONTEND_SOURCES)
+    log(f"frontend: {ms * 1e3:.1f} us/step (median {median_us:.1f}), {value:.1f} GB/s of field; "
+        f"fused kernel {launch_ms * 1e3:.1f} us = {achieved:.0f} GB/s algorithmic; beta={total_bits / n:.4f}")
+    cpu = None
+    if args.cpu_seconds > 0:
+        planes = 16
+        sub = x[:planes]
+        passes, t_total = 0, 0.0
+        while passes == 0 or (t_total < args.cpu_seconds and passes < 5):
+            t1 = time.perf_counter()
+            q = lz.lorenzo_codes(sub, inv, radius)
+            hh = oracle.histogram(q, A)
+            bk = oracle.codebook(hh)
+            oracle.encode(q, bk, chunk)
+            t_total += time.perf_counter() - t1
+            passes += 1
+        per = t_total / passes
+        cpu = {"value": round(sub.nbytes / per / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{passes} pass(es) of front end + histogram + codebook + encode over the first "
+                         f"{planes} planes ({sub.size} values), numpy + serial C, {per:.2f} s per pass"}
+    return {
+        "metric": "front end + encode GB/s of float32 field",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "median_us_per_step": round(median_us, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32->u16",
+        "data": "synthetic",
+        "config": {"workload": f"lorenzo3d_{dim}cube_f32_radius{radius}", "n_values": n, "alphabet": A,
+                   "chunk_symbols": chunk, "nslabs": S, "total_bits": total_bits},
+        "roofline": {"bound": "hbm", "kernel": "lorenzo_hist_kernel", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
+                     "bytes_per_launch": alg_bytes, "avg_launch_us": round(launch_ms * 1e3, 2)},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -500,6 +634,9 @@ def main():
         return
     if args.mode == "decode":
         print(json.dumps(run_decode(args)), flush=True)
+        return
+    if args.mode == "frontend":
+        print(json.dumps(run_frontend(args)), flush=True)
         return
 
     import torch

@@ -122,6 +122,34 @@ hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32
                        size_t ws_bytes, uint32_t* d_status, void* stream);
 
 /*
+ * Fused front end for the paper's multi-byte input (Sec. 5.1.3: the
+ * quantization codes an SZ-style error-bounded compressor makes from a float
+ * field), so that stage 1 needs no pass of its own over the codes.
+ * d_field is float32[nz][ny][nx] in C order (flat index
+ * f = (i * ny + j) * nx + k); n = nz * ny * nx < 2^32.  For every element:
+ *   d = fminf(fmaxf(rint(x * inv_2eb), -2^24), 2^24) in float32 (rint
+ *       ties to even; fmaxf / fminf ignore a NaN operand, so NaN gives
+ *       -2^24) -- inv_2eb is 1 / (2 eb) for an absolute error bound eb;
+ *   e = the 3D Lorenzo residual of d: the mixed first difference along the
+ *       three axes, with d = 0 outside the grid (eight neighbours, signs
+ *       (-1)^(di + dj + dk));
+ *   d_codes[f] (uint16[n]) = e + radius if 1 <= e + radius <= 2 radius - 1,
+ *       else 0 (the outlier code); the alphabet is 2 radius.
+ * d_hist (uint32[2 radius]) is overwritten with the counts of the codes.
+ * If d_slab_hist is not NULL, it receives the per-slab counts exactly as
+ * hf_histogram would for d_codes (same nslabs rules, 2 radius <= 4096), ready
+ * for hf_encode.  Requirements (else HF_ERR_ARG): 1 <= radius <= 8192;
+ * inv_2eb finite and > 0; nx <= 8192 when ny > 1; d_field 4-byte and d_codes
+ * 2-byte aligned (16-byte alignment of both and nx % 8 == 0 take the
+ * vector path).  No device errors are possible.  One workgroup per slab
+ * streams its part of the field once, re-reads the plane before it (mostly
+ * from cache), and keeps the previous row's partial differences in LDS.
+ */
+hf_status hf_lorenzo_histogram(const float* d_field, uint32_t nz, uint32_t ny, uint32_t nx, float inv_2eb,
+                               uint32_t radius, uint16_t* d_codes, uint32_t* d_hist, uint32_t nslabs,
+                               uint32_t* d_slab_hist, void* stream);
+
+/*
  * Stages 2 and 3, codebook construction and canonization (Sec. 4.2,
  * Algorithm 1): from d_hist (uint32[book->alphabet]) fill every array of
  * *book (see hf_codebook).  Leaves are sorted by (count, symbol); code

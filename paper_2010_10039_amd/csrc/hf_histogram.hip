@@ -209,6 +209,13 @@ __global__ __launch_bounds__(kHistThreads) void hist_reduce_kernel(const uint32_
   }
 }
 
+hipError_t launch_slab_hist_reduce(const uint32_t* slab_hist, uint32_t nslabs, uint32_t A, uint32_t* hist,
+                                   hipStream_t stream) {
+  hist_reduce_kernel<<<(nslabs + kReduceRows - 1) / kReduceRows, kHistThreads, 0, stream>>>(slab_hist, nslabs, A,
+                                                                                            hist);
+  return hipGetLastError();
+}
+
 // Batched stage 1: workgroup i counts slab g of stream s for the work item
 // items[i] = streams[s].item0 + g and stores the slab's counts.  The LDS
 // holds lds_words words: as many interleaved replicas of the alphabet as fit.

@@ -57,6 +57,17 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
                             size_t ws_bytes, uint32_t* status, int num_cus, hipStream_t stream,
                             const KernelTimer& timer);
 
+// hist[b] += sum over slabs of slab_hist[g * A + b] (hist zeroed beforehand).
+hipError_t launch_slab_hist_reduce(const uint32_t* slab_hist, uint32_t nslabs, uint32_t A, uint32_t* hist,
+                                   hipStream_t stream);
+
+// Fused prequantization + 3D Lorenzo residual + histogram of a float field
+// (nz, ny, nx) in C order; with slab_hist also the per-slab counts.
+size_t lorenzo_lds_bytes(uint32_t ny, uint32_t nx, uint32_t radius);
+hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, uint32_t nx, float r, uint32_t radius,
+                                    uint16_t* codes, uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist,
+                                    int num_cus, hipStream_t stream, const KernelTimer& timer);
+
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.
 size_t codebook_workspace_bytes(uint32_t alphabet);

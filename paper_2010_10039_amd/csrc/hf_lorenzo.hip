@@ -1,0 +1,351 @@
+// hf_lorenzo.hip -- fused front end: error-bounded prequantization, 3D
+// Lorenzo prediction and histogramming in one pass over a float32 field.
+//
+// The paper's multi-byte input (Sec. 5.1.3) is the code stream an SZ-style
+// compressor makes from a float field: every value times r = 1 / (2 eb) is
+// rounded to an integer d, the Lorenzo predictor's residual e of those
+// integers is offset by a radius, and residuals outside the code range become
+// code 0 (an outlier).  Making the codes and counting them in one kernel
+// saves the histogram's own pass over the codes.
+//
+// Work split: one workgroup per slab of the encoder's block partition, so the
+// per-slab counts the encoder wants come out directly.  In flat C order,
+// f = (i * ny + j) * nx + k, the residual is taken as three first
+// differences (P = ny * nx):
+//   u(f) = d(f) - [i > 0] d(f - P)
+//   t(f) = u(f) - [k > 0] u(f - 1)
+//   e(f) = t(f) - [j > 0] t(f - nx)
+// u reads the field twice: at f (streamed from HBM once) and one plane back
+// (read by the workgroup two slabs earlier at about the same time, so mostly
+// a cache hit).  The fastest-axis neighbour comes from the next-lower lane.
+// t one row back comes from a ring of t values in LDS that the workgroup
+// itself wrote (a prologue fills it with the row just before the slab).
+#include <math.h>
+
+#include <algorithm>
+
+#include "hf_device.h"
+#include "hf_kernels.h"
+
+namespace hf {
+
+namespace {
+
+constexpr int kLzThreads = 256;
+constexpr int kLzVec = 8;                          // consecutive elements per lane and step
+constexpr uint32_t kLzStep = kLzThreads * kLzVec;  // elements per workgroup and step
+constexpr float kLzClamp = 16777216.0f;            // |d| <= 2^24 keeps every residual in int32
+
+// n / d for every 32-bit n with one multiply-high (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", PLDI 1994, Sec. 4):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, n / d = (mulhi(m, n) + n) >> l
+// evaluated in 64 bits.
+struct FastDiv {
+  uint32_t d;
+  uint32_t m;
+  uint32_t l;
+};
+
+FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t m = (((1ull << l) - d) << 32) / d + 1;
+  return FastDiv{d, (uint32_t)m, l};
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((uint64_t)__umulhi(n, f.m) + n) >> f.l);
+}
+
+__device__ __forceinline__ uint32_t fmod_(uint32_t n, const FastDiv& f) { return n - fdiv(n, f) * f.d; }
+
+struct LzArgs {
+  const float* x;
+  uint16_t* codes;
+  uint32_t* hist;       // zeroed by workgroup 0 when slab_hist is set (hist_reduce adds), else beforehand
+  uint32_t* slab_hist;  // [nslabs][A] or null
+  uint32_t n;
+  uint32_t nx;
+  uint32_t plane;  // ny * nx
+  FastDiv div_nx;
+  FastDiv div_plane;
+  float r;
+  int radius;
+  uint32_t A;          // 2 * radius
+  uint32_t rep_shift;  // log2 of the LDS histogram replicas
+  uint32_t ring_mask;  // ring words - 1; 0 when ny == 1 (no row above ever exists)
+  uint32_t nslabs;
+  uint32_t nblocks;
+};
+
+// Prequantization: x * r rounded to the nearest integer, ties to even,
+// clamped to [-2^24, 2^24] by fmaxf / fminf, which pass over a NaN operand
+// (so NaN gives -2^24).
+__device__ __forceinline__ int prequant(float x, float r) {
+  return (int)fminf(fmaxf(rintf(x * r), -kLzClamp), kLzClamp);
+}
+
+// u(f) = d(f) - [f >= P] d(f - P)
+__device__ __forceinline__ int u_at(const LzArgs& a, uint32_t f) {
+  const int own = prequant(a.x[f], a.r);
+  return f >= a.plane ? own - prequant(a.x[f - a.plane], a.r) : own;
+}
+
+// t(f) = u(f) - [k > 0] u(f - 1)
+__device__ __forceinline__ int t_at(const LzArgs& a, uint32_t f) {
+  const int u = u_at(a, f);
+  return fmod_(f, a.div_nx) ? u - u_at(a, f - 1) : u;
+}
+
+// j > 0: the row above f exists inside its plane.
+__device__ __forceinline__ bool row_above(const LzArgs& a, uint32_t f) { return fmod_(f, a.div_plane) >= a.nx; }
+
+__device__ __forceinline__ uint32_t code_of(int e, int radius) {
+  const int q = e + radius;
+  return (uint32_t)(q - 1) < (uint32_t)(2 * radius - 1) ? (uint32_t)q : 0u;
+}
+
+__device__ __forceinline__ void load8(const float* p, float v[kLzVec]) {
+  const float4 a = *(const float4*)p;
+  const float4 b = *(const float4*)(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// Loads of one vector step, issued one step ahead: the lane's 8 values, the
+// 8 one plane back, the value just before the group and its plane-back
+// value (lane 0 of a wave uses the last two; the other lanes get that u from
+// their lower neighbour).  All six loads are always issued, so the wait for
+// a step's data is a fixed count behind the next step's loads: an index with
+// nothing to read (no plane back, no value before, a group past the end)
+// reads a valid address instead and its value is masked off.
+struct LzFetch {
+  float o[kLzVec];
+  float b[kLzVec];
+  float lo;
+  float lb;
+};
+
+__device__ __forceinline__ void fetch_step(const LzArgs& a, uint64_t f, uint64_t s_hi, LzFetch& v) {
+  const uint32_t fo = f + kLzVec <= s_hi ? (uint32_t)f : 0u;
+  const uint32_t fl = fo > 0 ? fo - 1 : 0u;
+  load8(a.x + (fo >= a.plane ? fo - a.plane : fo), v.b);
+  load8(a.x + fo, v.o);
+  v.lb = a.x[fl >= a.plane ? fl - a.plane : fl];
+  v.lo = a.x[fl];
+}
+
+// Codes of one lane's group from t and the row-above values: the 16-byte
+// store on the vector path, one store per element otherwise; LDS counts.
+__device__ __forceinline__ uint32_t lz_code(const LzArgs& a, int t, int prev) { return code_of(t - prev, a.radius); }
+
+// One whole step on the vector path: group f = base + 8 tid, every lane's
+// group inside the slab.  Uses `cur`, fetches the step after into `nxt`,
+// writes t to the ring, reads the row above after a barrier, and stores
+// codes and counts.
+__device__ __forceinline__ void vec_step(const LzArgs& a, uint64_t base, uint64_t s_hi, int* ring, char* subr,
+                                         uint32_t hshift, bool lane0, const LzFetch& cur, LzFetch& nxt) {
+  const uint32_t f = (uint32_t)(base + threadIdx.x * kLzVec);
+  fetch_step(a, (uint64_t)f + kLzStep, s_hi, nxt);
+  // Take all of `cur` here, on every path: the compiler then knows those
+  // registers are written before the step after reloads them, and waits
+  // only for this step's data, never for the loads just issued.
+  asm volatile("" ::"v"(cur.o[0]), "v"(cur.o[1]), "v"(cur.o[2]), "v"(cur.o[3]), "v"(cur.o[4]), "v"(cur.o[5]),
+               "v"(cur.o[6]), "v"(cur.o[7]), "v"(cur.b[0]), "v"(cur.b[1]), "v"(cur.b[2]), "v"(cur.b[3]),
+               "v"(cur.b[4]), "v"(cur.b[5]), "v"(cur.b[6]), "v"(cur.b[7]), "v"(cur.lo), "v"(cur.lb));
+  const int mb = f >= a.plane ? -1 : 0;
+  int u[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) u[e] = prequant(cur.o[e], a.r) - (prequant(cur.b[e], a.r) & mb);
+  const int up = __shfl_up(u[kLzVec - 1], 1, 64);
+  const int own_left = prequant(cur.lo, a.r) - (prequant(cur.lb, a.r) & (f - 1 >= a.plane ? -1 : 0));
+  const int left = lane0 ? own_left : up;
+  const bool k0 = fmod_(f, a.div_nx) == 0;
+  int t[kLzVec];
+  t[0] = u[0] - (k0 ? 0 : left);
+#pragma unroll
+  for (int e = 1; e < kLzVec; ++e) t[e] = u[e] - u[e - 1];
+  if (a.ring_mask) {
+    int4* w = (int4*)(ring + (f & a.ring_mask));
+    w[0] = make_int4(t[0], t[1], t[2], t[3]);
+    w[1] = make_int4(t[4], t[5], t[6], t[7]);
+  }
+  __syncthreads();
+  int prev[kLzVec];
+  if (a.ring_mask && row_above(a, f)) {
+    const int4* rd = (const int4*)(ring + ((f - a.nx) & a.ring_mask));
+    const int4 p0 = rd[0];
+    const int4 p1 = rd[1];
+    prev[0] = p0.x; prev[1] = p0.y; prev[2] = p0.z; prev[3] = p0.w;
+    prev[4] = p1.x; prev[5] = p1.y; prev[6] = p1.z; prev[7] = p1.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < kLzVec; ++e) prev[e] = 0;
+  }
+  __syncthreads();  // the next step rewrites ring slots read above
+  uint32_t q[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) q[e] = lz_code(a, t[e], prev[e]);
+  *(uint4*)(a.codes + f) = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16),
+                                      q[6] | (q[7] << 16));
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) atomicAdd((uint32_t*)(subr + (q[e] << hshift)), 1u);
+}
+
+// One step element by element (groups that are not whole, unaligned
+// fields): the same three differences from direct loads.
+__device__ __forceinline__ void elem_step(const LzArgs& a, uint64_t base, uint64_t s_hi, int* ring, char* subr,
+                                          uint32_t hshift) {
+  const uint64_t f64 = base + threadIdx.x * kLzVec;
+  const uint32_t f = (uint32_t)f64;  // meaningful only while f64 < s_hi
+  int t[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) {
+    const bool in = f64 + e < s_hi;
+    const uint32_t fe = f + e;
+    t[e] = in ? t_at(a, fe) : 0;
+    if (a.ring_mask && in) ring[fe & a.ring_mask] = t[e];
+  }
+  __syncthreads();
+  int prev[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) {
+    const uint32_t fe = f + e;
+    prev[e] = (a.ring_mask && f64 + e < s_hi && row_above(a, fe)) ? ring[(fe - a.nx) & a.ring_mask] : 0;
+  }
+  __syncthreads();  // the next step rewrites ring slots read above
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) {
+    if (f64 + e < s_hi) {
+      const uint32_t q = lz_code(a, t[e], prev[e]);
+      a.codes[f + e] = (uint16_t)q;
+      atomicAdd((uint32_t*)(subr + (q << hshift)), 1u);
+    }
+  }
+}
+
+// kVec: nx % 8 == 0 and both arrays 16-byte aligned, so a lane's 8
+// elements share one row and move as two 16-byte vectors, fetched one step
+// ahead (two register sets, alternating).  The whole steps of a slab run
+// on that path; a last partial step (and every step when !kVec) runs
+// element by element.
+template <bool kVec>
+__global__ __launch_bounds__(kLzThreads) void lorenzo_hist_kernel(LzArgs a) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t reps = 1u << a.rep_shift;
+  uint32_t* sub = lds;
+  int* ring = (int*)(lds + ((a.A * reps + 3) & ~3u));
+  for (uint32_t i = tid; i < a.A * reps; i += kLzThreads) sub[i] = 0;
+  if (a.slab_hist && blockIdx.x == 0)
+    for (uint32_t b = tid; b < a.A; b += kLzThreads) a.hist[b] = 0;
+
+  const uint32_t g = blockIdx.x;
+  const uint64_t s_lo = slab_begin(g, a.nblocks, a.nslabs, a.n);
+  const uint64_t s_hi = slab_begin(g + 1, a.nblocks, a.nslabs, a.n);
+  if (a.ring_mask) {
+    const uint32_t p_lo = s_lo > a.nx ? (uint32_t)s_lo - a.nx : 0;
+    for (uint32_t f = p_lo + tid; f < s_lo; f += kLzThreads) ring[f & a.ring_mask] = t_at(a, f);
+  }
+  __syncthreads();
+
+  char* const subr = (char*)(sub + (tid & (reps - 1)));
+  const uint32_t hshift = a.rep_shift + 2;
+  uint64_t base = s_lo;
+  if (kVec) {
+    const uint64_t v_end = s_lo + (s_hi - s_lo) / kLzStep * kLzStep;
+    const bool lane0 = (tid & 63) == 0;
+    LzFetch va, vb;
+    fetch_step(a, s_lo + tid * kLzVec, s_hi, va);
+    for (; base + 2 * kLzStep <= v_end; base += 2 * kLzStep) {
+      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb);
+      vec_step(a, base + kLzStep, s_hi, ring, subr, hshift, lane0, vb, va);
+    }
+    if (base < v_end) {
+      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb);
+      base += kLzStep;
+    }
+  }
+  for (; base < s_hi; base += kLzStep) elem_step(a, base, s_hi, ring, subr, hshift);
+  __syncthreads();
+  if (a.slab_hist) {
+    uint32_t* row = a.slab_hist + (uint64_t)g * a.A;
+    for (uint32_t b = tid; b < a.A; b += kLzThreads) {
+      uint32_t c = 0;
+      for (uint32_t rr = 0; rr < reps; ++rr) c += sub[(b << a.rep_shift) + rr];
+      row[b] = c;
+    }
+  } else {
+    for (uint32_t b = tid; b < a.A; b += kLzThreads) {
+      uint32_t c = 0;
+      for (uint32_t rr = 0; rr < reps; ++rr) c += sub[(b << a.rep_shift) + rr];
+      if (c) atomicAdd(a.hist + b, c);
+    }
+  }
+}
+
+uint32_t pow2_at_least(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+size_t lorenzo_lds_bytes(uint32_t ny, uint32_t nx, uint32_t radius) {
+  const uint32_t A = 2 * radius;
+  uint32_t shift = 0;
+  while (shift < 4 && A * (2u << shift) * 4u <= (16u << 10)) ++shift;
+  const uint32_t hist_words = (A * (1u << shift) + 3) & ~3u;
+  const uint32_t ring_words = ny > 1 ? pow2_at_least(kLzStep + nx) : 0;
+  return (size_t)(hist_words + ring_words) * 4;
+}
+
+hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, uint32_t nx, float r, uint32_t radius,
+                                    uint16_t* codes, uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist,
+                                    int num_cus, hipStream_t stream, const KernelTimer& timer) {
+  const uint64_t n = (uint64_t)nz * ny * nx;
+  const uint32_t A = 2 * radius;
+  hipError_t e;
+  if (n == 0) return launch_fill_u32(hist, A, 0u, stream);
+  LzArgs a;
+  a.x = x;
+  a.codes = codes;
+  a.hist = hist;
+  a.slab_hist = slab_hist;
+  a.n = (uint32_t)n;
+  a.nx = nx;
+  a.plane = ny * nx;
+  a.div_nx = make_fastdiv(nx);
+  a.div_plane = make_fastdiv(ny * nx);
+  a.r = r;
+  a.radius = (int)radius;
+  a.A = A;
+  a.rep_shift = 0;
+  while (a.rep_shift < 4 && A * (2u << a.rep_shift) * 4u <= (16u << 10)) ++a.rep_shift;
+  a.ring_mask = ny > 1 ? pow2_at_least(kLzStep + nx) - 1 : 0;
+  a.nblocks = (uint32_t)((n + kSlabBlock - 1) / kSlabBlock);
+  if (slab_hist) {
+    a.nslabs = nslabs;
+  } else {
+    e = launch_fill_u32(hist, A, 0u, stream);
+    if (e != hipSuccess) return e;
+    a.nslabs = (uint32_t)std::min<uint64_t>((uint64_t)num_cus * 4, a.nblocks);
+  }
+  const size_t lds = lorenzo_lds_bytes(ny, nx, radius);
+  const bool vec = nx % kLzVec == 0 && ((uintptr_t)x & 15) == 0 && ((uintptr_t)codes & 15) == 0;
+  const void* fn = vec ? (const void*)lorenzo_hist_kernel<true> : (const void*)lorenzo_hist_kernel<false>;
+  if (lds > (64u << 10)) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  timer.before(stream);
+  if (vec)
+    lorenzo_hist_kernel<true><<<a.nslabs, kLzThreads, lds, stream>>>(a);
+  else
+    lorenzo_hist_kernel<false><<<a.nslabs, kLzThreads, lds, stream>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  timer.after(stream);
+  if (slab_hist) return launch_slab_hist_reduce(slab_hist, nslabs, A, hist, stream);
+  return hipSuccess;
+}
+
+}  // namespace hf

@@ -75,6 +75,8 @@ _lib.hf_encode.restype = ctypes.c_int
 _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
                                  _SZ, _P, _P]
 _lib.hf_decode_check.restype = ctypes.c_int
+_lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P]
+_lib.hf_lorenzo_histogram.restype = ctypes.c_int
 _lib.hf_decode_workspace_bytes.argtypes = []
 _lib.hf_decode_workspace_bytes.restype = _SZ
 _lib.hf_decode.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _SZ, _P, _P]
@@ -211,6 +213,27 @@ def hf_histogram(sym: torch.Tensor, alphabet: int, hist: torch.Tensor | None = N
                              _ptr(ws), 0 if ws is None else ws.numel(), _ptr(status), _stream()),
            "hf_histogram")
     return hist
+
+
+def hf_lorenzo_histogram(field: torch.Tensor, dims, inv_2eb: float, radius: int,
+                         codes: torch.Tensor | None = None, hist: torch.Tensor | None = None,
+                         nslabs: int = 0, slab_hist: torch.Tensor | None = None):
+    """Quantization codes (int16 tensor holding uint16) of the float32 field
+    of shape dims = (nz, ny, nx) and their histogram (int32[2 radius]); with
+    `slab_hist` (int32[nslabs * 2 radius]) also the per-slab counts for
+    hf_encode.  Returns (codes, hist)."""
+    if field.dtype != torch.float32 or not field.is_contiguous():
+        raise TypeError("the field must be a contiguous float32 tensor")
+    nz, ny, nx = (int(v) for v in dims)
+    if field.numel() != nz * ny * nx:
+        raise ValueError(f"field has {field.numel()} elements, dims {dims} need {nz * ny * nx}")
+    if codes is None:
+        codes = torch.empty(field.numel(), dtype=torch.int16, device=field.device)
+    if hist is None:
+        hist = torch.empty(2 * radius, dtype=torch.int32, device=field.device)
+    _check(_lib.hf_lorenzo_histogram(_ptr(field), nz, ny, nx, float(inv_2eb), radius, _ptr(codes), _ptr(hist),
+                                     nslabs, _ptr(slab_hist), _stream()), "hf_lorenzo_histogram")
+    return codes, hist
 
 
 def hf_build_codebook(hist: torch.Tensor, book: Codebook | None = None, ws: torch.Tensor | None = None,

@@ -87,6 +87,27 @@ def lorenzo_field(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01, eb
     return x.numpy(), eb
 
 
+def random_field(shape, seed: int = 0, nwaves: int = 6, noise_rel_std: float = 0.01) -> np.ndarray:
+    """A small float32 field of any 3D shape for tests: a sum of `nwaves`
+    random sinusoids over the grid (amplitudes U(0.5, 1.5), integer
+    frequencies 1..4 per axis, random phases) plus Gaussian noise of standard
+    deviation noise_rel_std * std.  Evaluated directly in float64, so meant
+    for grids of a few million points at most."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = (int(v) for v in shape)
+    iz = np.arange(nz, dtype=np.float64)[:, None, None] / max(nz, 1)
+    iy = np.arange(ny, dtype=np.float64)[None, :, None] / max(ny, 1)
+    ix = np.arange(nx, dtype=np.float64)[None, None, :] / max(nx, 1)
+    f = np.zeros((nz, ny, nx), dtype=np.float64)
+    for _ in range(nwaves):
+        a = rng.uniform(0.5, 1.5)
+        u, v, w = rng.integers(1, 5, size=3)
+        f += a * np.sin(2.0 * math.pi * (u * iz + v * iy + w * ix) + rng.uniform(0.0, 2.0 * math.pi))
+    sd = float(f.std()) if f.size > 1 else 1.0
+    f += rng.normal(0.0, noise_rel_std * (sd if sd > 0 else 1.0), size=f.shape)
+    return f.astype(np.float32)
+
+
 def lorenzo_quant_codes(dim: int = 512, seed: int = 0, noise_rel_std: float = 0.01,
                         eb_rel: float = 1e-4, radius: int = 512) -> np.ndarray:
     """Error-bounded quantization codes of a smooth 3D field (SZ-style).

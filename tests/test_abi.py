@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ("hf_histogram", "hf_build_codebook", "hf_encode", "hf_decode", "hf_decode_check",
-                 "hf_workspace_bytes", "hf_decode_workspace_bytes", "hf_bound_words"):
+                 "hf_lorenzo_histogram", "hf_workspace_bytes", "hf_decode_workspace_bytes", "hf_bound_words"):
         assert want in names
 
 
@@ -115,6 +115,28 @@ def test_decoder_argument_checks(lib):
     assert lib.hf_decode(d, d, 100, 2, 4096, ctypes.byref(book), d, P(0x100004), need, d, None) == 2
     lib.hf_status_string.restype = ctypes.c_char_p
     assert b"decode" in lib.hf_status_string(21)
+
+
+def test_front_end_argument_checks(lib):
+    P = ctypes.c_void_p
+    U32, F = ctypes.c_uint32, ctypes.c_float
+    f = lib.hf_lorenzo_histogram
+    f.argtypes = [P, U32, U32, U32, F, U32, P, P, U32, P, P]
+    x, c, h, sh = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
+    ok = dict(x=x, nz=8, ny=16, nx=512, r=100.0, radius=512, c=c, h=h, s=0, sh=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["x"], a["nz"], a["ny"], a["nx"], a["r"], a["radius"], a["c"], a["h"], a["s"], a["sh"], None)
+
+    assert call(radius=0) == 1 and call(radius=8193) == 1
+    assert call(r=0.0) == 1 and call(r=-1.0) == 1 and call(r=float("inf")) == 1 and call(r=float("nan")) == 1
+    assert call(h=None) == 1 and call(x=None) == 1 and call(c=None) == 1
+    assert call(x=P(0x10002)) == 1 and call(c=P(0x20001)) == 1            # misaligned
+    assert call(nz=1 << 12, ny=1 << 10, nx=1 << 10) == 1                   # n = 2^32
+    assert call(nz=1, ny=2, nx=8193) == 1                                  # row longer than the LDS ring
+    assert call(sh=sh, s=0) == 1 and call(sh=sh, s=17) == 1                # 16 blocks of 4096
+    assert call(sh=sh, s=4, radius=4096) == 1                              # alphabet 8192 > 4096 with slabs
 
 
 def test_slab_count_bounds(lib):

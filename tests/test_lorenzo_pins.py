@@ -3,7 +3,8 @@ that do not come from the oracle itself.
 
 - Prequantization: values that are exact multiples of 2 eb (a power-of-two
   bound, so every product is exact) give their multiple; exact half-way
-  values round to the even neighbour; IEEE specials clamp as documented.
+  values round to the even neighbour; infinities and huge values clamp to
+  +-2^24 and NaN to -2^24 (C's fmax / fmin ignore a NaN operand).
 - Residual: summing it back along the three axes (the predictor's inverse,
   a 3D prefix sum) recovers the prequantized integers; on tiny grids it
   equals the eight-neighbour inclusion-exclusion sum evaluated point by
@@ -61,8 +62,10 @@ def test_prequantize_rounding_error_at_most_half():
 
 
 def test_prequantize_specials_clamp():
+    # C99 fmax / fmin return the other operand when one is NaN, so NaN
+    # clamps to the lower bound
     x = np.float32([1e30, -1e30, np.inf, -np.inf, np.nan, 16777216.0 * 4, -0.0])
-    assert list(lz.prequantize(x, 1.0)) == [1 << 24, -(1 << 24), 1 << 24, -(1 << 24), 0, 1 << 24, 0]
+    assert list(lz.prequantize(x, 1.0)) == [1 << 24, -(1 << 24), 1 << 24, -(1 << 24), -(1 << 24), 1 << 24, 0]
 
 
 # -- residual ----------------------------------------------------------------
