@@ -576,7 +576,7 @@ def run_frontend(args):
     value = n * 4 / (ms * 1e-3) / 1e9
     alg_bytes = n * 4 + n * 2 + S * A * 4
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("lorenzo_hist_kernel", "lorenzo_hist_lorenzo512_hbm_traffic.txt", FRONTEND_SOURCES)
+    traffic = measured_traffic("lorenzo_chain_kernel", "lorenzo_chain_lorenzo512_hbm_traffic.txt", FRONTEND_SOURCES)
     log(f"frontend: {ms * 1e3:.1f} us/step (median {median_us:.1f}), {value:.1f} GB/s of field; "
         f"fused kernel {launch_ms * 1e3:.1f} us = {achieved:.0f} GB/s algorithmic; beta={total_bits / n:.4f}")
     cpu = None
@@ -612,7 +612,7 @@ def run_frontend(args):
         "data": "synthetic",
         "config": {"workload": f"lorenzo3d_{dim}cube_f32_radius{radius}", "n_values": n, "alphabet": A,
                    "chunk_symbols": chunk, "nslabs": S, "total_bits": total_bits},
-        "roofline": {"bound": "hbm", "kernel": "lorenzo_hist_kernel", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "lorenzo_chain_kernel", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
                      "bytes_per_launch": alg_bytes, "avg_launch_us": round(launch_ms * 1e3, 2)},

@@ -284,6 +284,188 @@ __global__ __launch_bounds__(kLzThreads) void lorenzo_hist_kernel(LzArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chained slabs.  When every slab has the same length L, L is a whole number
+// of steps and a plane is D = P / L slabs, slab g's values one plane back
+// are exactly slab g - D.  A workgroup of kChain sub-groups (256 threads
+// each) then runs the slabs of kChain consecutive planes that sit at the
+// same place in their planes, in lockstep: sub-group k publishes its
+// prequantized d in LDS, and sub-group k + 1 takes its plane-back values
+// from there instead of reading the field again.  Only sub-group 0 reads
+// the plane before the chain from memory, so the field is read
+// (kChain + 1) / kChain times instead of twice.
+
+constexpr int kChain = 4;
+constexpr int kChainThreads = kChain * kLzThreads;
+
+// As fetch_step; the plane-back vector is real only for sub-group 0 (the
+// others read their own values a second time, a cache hit, so the load
+// count stays fixed), and the plane-back value before the group only for
+// lane 0.
+__device__ __forceinline__ void fetch_chain(const LzArgs& a, uint64_t f, uint64_t s_hi, bool first_sub, bool lane0,
+                                            LzFetch& v) {
+  const uint32_t fo = f + kLzVec <= s_hi ? (uint32_t)f : 0u;
+  const uint32_t fl = fo > 0 ? fo - 1 : 0u;
+  load8(a.x + (first_sub && fo >= a.plane ? fo - a.plane : fo), v.b);
+  load8(a.x + fo, v.o);
+  v.lb = a.x[lane0 && fl >= a.plane ? fl - a.plane : fl];
+  v.lo = a.x[fl];
+}
+
+struct ChainLane {
+  bool active;     // this sub-group has a slab (the last chain may be short)
+  bool first_sub;  // sub-group 0: plane-back values come from memory
+  bool publish;    // the next sub-group has a slab and reads d from here
+  bool lane0;
+  uint32_t lt;     // thread index inside the sub-group
+  uint64_t s_hi;   // end of the slab (0 when inactive: fetches read index 0)
+  int* ring;
+  char* subr;
+  uint32_t hshift;
+  int* xb_out;
+  const int* xb_in;
+};
+
+// One step of sub-group k at group f64: uses `cur` (fetched two steps
+// earlier) and fetches the step two ahead into `ahead`.
+__device__ __forceinline__ void chain_step(const LzArgs& a, const ChainLane& c, uint64_t f64, const LzFetch& cur,
+                                           LzFetch& ahead) {
+  const uint32_t f = (uint32_t)f64;
+  fetch_chain(a, f64 + 2 * kLzStep, c.s_hi, c.first_sub, c.lane0, ahead);
+  asm volatile("" ::"v"(cur.o[0]), "v"(cur.o[1]), "v"(cur.o[2]), "v"(cur.o[3]), "v"(cur.o[4]), "v"(cur.o[5]),
+               "v"(cur.o[6]), "v"(cur.o[7]), "v"(cur.b[0]), "v"(cur.b[1]), "v"(cur.b[2]), "v"(cur.b[3]),
+               "v"(cur.b[4]), "v"(cur.b[5]), "v"(cur.b[6]), "v"(cur.b[7]), "v"(cur.lo), "v"(cur.lb));
+  int d[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) d[e] = prequant(cur.o[e], a.r);
+  if (c.publish) {
+    int4* w = (int4*)(c.xb_out + c.lt * kLzVec);
+    w[0] = make_int4(d[0], d[1], d[2], d[3]);
+    w[1] = make_int4(d[4], d[5], d[6], d[7]);
+  }
+  int db[kLzVec];
+  if (c.first_sub) {  // uniform per wave
+    const int mb = f >= a.plane ? -1 : 0;
+#pragma unroll
+    for (int e = 0; e < kLzVec; ++e) db[e] = prequant(cur.b[e], a.r) & mb;
+  }
+  __syncthreads();  // d published; the last step's ring reads are done
+  if (!c.first_sub) {
+    const int4* rd = (const int4*)(c.xb_in + c.lt * kLzVec);
+    const int4 p0 = rd[0];
+    const int4 p1 = rd[1];
+    db[0] = p0.x; db[1] = p0.y; db[2] = p0.z; db[3] = p0.w;
+    db[4] = p1.x; db[5] = p1.y; db[6] = p1.z; db[7] = p1.w;
+  }
+  int u[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) u[e] = d[e] - db[e];
+  const int up = __shfl_up(u[kLzVec - 1], 1, 64);
+  const int own_left = prequant(cur.lo, a.r) - (prequant(cur.lb, a.r) & (f - 1 >= a.plane ? -1 : 0));
+  const int left = c.lane0 ? own_left : up;
+  const bool k0 = fmod_(f, a.div_nx) == 0;
+  int t[kLzVec];
+  t[0] = u[0] - (k0 ? 0 : left);
+#pragma unroll
+  for (int e = 1; e < kLzVec; ++e) t[e] = u[e] - u[e - 1];
+  if (c.active && a.ring_mask) {
+    int4* w = (int4*)(c.ring + (f & a.ring_mask));
+    w[0] = make_int4(t[0], t[1], t[2], t[3]);
+    w[1] = make_int4(t[4], t[5], t[6], t[7]);
+  }
+  __syncthreads();  // t in the ring; the published d has been read
+  if (!c.active) return;
+  int prev[kLzVec];
+  if (a.ring_mask && row_above(a, f)) {
+    const int4* rd = (const int4*)(c.ring + ((f - a.nx) & a.ring_mask));
+    const int4 p0 = rd[0];
+    const int4 p1 = rd[1];
+    prev[0] = p0.x; prev[1] = p0.y; prev[2] = p0.z; prev[3] = p0.w;
+    prev[4] = p1.x; prev[5] = p1.y; prev[6] = p1.z; prev[7] = p1.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < kLzVec; ++e) prev[e] = 0;
+  }
+  uint32_t q[kLzVec];
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) q[e] = lz_code(a, t[e], prev[e]);
+  *(uint4*)(a.codes + f) = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16),
+                                      q[6] | (q[7] << 16));
+#pragma unroll
+  for (int e = 0; e < kLzVec; ++e) atomicAdd((uint32_t*)(c.subr + (q[e] << c.hshift)), 1u);
+}
+
+// Workgroup w runs chain (plane group w / D, place w % D): sub-group k takes
+// slab (plane group * kChain + k) * D + w % D.  L is the slab length in
+// values, nz the number of planes.
+__global__ __launch_bounds__(kChainThreads) void lorenzo_chain_kernel(LzArgs a, uint32_t D, uint32_t L, uint32_t nz) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const uint32_t k = threadIdx.x / kLzThreads;
+  const uint32_t lt = threadIdx.x % kLzThreads;
+  const uint32_t reps = 1u << a.rep_shift;
+  const uint32_t hist_words = (a.A * reps + 3) & ~3u;
+  const uint32_t ring_words = a.ring_mask ? a.ring_mask + 1 : 0;
+  for (uint32_t i = threadIdx.x; i < kChain * hist_words; i += kChainThreads) lds[i] = 0;
+  if (a.slab_hist && blockIdx.x == 0)
+    for (uint32_t b = threadIdx.x; b < a.A; b += kChainThreads) a.hist[b] = 0;
+
+  const uint32_t plane = (blockIdx.x / D) * kChain + k;
+  const uint32_t g = plane * D + blockIdx.x % D;
+  ChainLane c;
+  c.active = plane < nz;
+  c.first_sub = k == 0;
+  c.publish = k + 1 < kChain && plane + 1 < nz;
+  c.lane0 = (lt & 63) == 0;
+  c.lt = lt;
+  const uint64_t s_lo = c.active ? (uint64_t)g * L : 0;
+  c.s_hi = c.active ? s_lo + L : 0;
+  uint32_t* sub = lds + k * hist_words;
+  c.ring = (int*)(lds + kChain * hist_words) + k * ring_words;
+  c.subr = (char*)(sub + (lt & (reps - 1)));
+  c.hshift = a.rep_shift + 2;
+  int* xb = (int*)(lds + kChain * (hist_words + ring_words));
+  c.xb_out = xb + k * kLzStep;
+  c.xb_in = xb + (k > 0 ? k - 1 : 0) * kLzStep;
+  if (c.active && a.ring_mask) {
+    const uint32_t p_lo = s_lo > a.nx ? (uint32_t)s_lo - a.nx : 0;
+    for (uint32_t f = p_lo + lt; f < s_lo; f += kLzThreads) c.ring[f & a.ring_mask] = t_at(a, f);
+  }
+  __syncthreads();
+
+  // Two steps in flight: with one 16-wave workgroup per CU, a single step
+  // ahead keeps too few bytes in flight to cover the memory latency.  Three
+  // register sets rotate (step s uses set s % 3 and fills set (s + 2) % 3).
+  const uint32_t steps = L / kLzStep;
+  const uint64_t f0 = s_lo + lt * kLzVec;
+  LzFetch va, vb, vc;
+  fetch_chain(a, f0, c.s_hi, c.first_sub, c.lane0, va);
+  fetch_chain(a, f0 + kLzStep, c.s_hi, c.first_sub, c.lane0, vb);
+  uint32_t st = 0;
+  for (; st + 3 <= steps; st += 3) {
+    chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc);
+    chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va);
+    chain_step(a, c, f0 + (uint64_t)(st + 2) * kLzStep, vc, vb);
+  }
+  if (st < steps) chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc);
+  if (st + 1 < steps) chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va);
+  __syncthreads();
+  if (!c.active) return;
+  if (a.slab_hist) {
+    uint32_t* row = a.slab_hist + (uint64_t)g * a.A;
+    for (uint32_t b = lt; b < a.A; b += kLzThreads) {
+      uint32_t cnt = 0;
+      for (uint32_t rr = 0; rr < reps; ++rr) cnt += sub[(b << a.rep_shift) + rr];
+      row[b] = cnt;
+    }
+  } else {
+    for (uint32_t b = lt; b < a.A; b += kLzThreads) {
+      uint32_t cnt = 0;
+      for (uint32_t rr = 0; rr < reps; ++rr) cnt += sub[(b << a.rep_shift) + rr];
+      if (cnt) atomicAdd(a.hist + b, cnt);
+    }
+  }
+}
+
 uint32_t pow2_at_least(uint32_t v) {
   uint32_t p = 1;
   while (p < v) p <<= 1;
@@ -332,8 +514,31 @@ hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, ui
     if (e != hipSuccess) return e;
     a.nslabs = (uint32_t)std::min<uint64_t>((uint64_t)num_cus * 4, a.nblocks);
   }
-  const size_t lds = lorenzo_lds_bytes(ny, nx, radius);
   const bool vec = nx % kLzVec == 0 && ((uintptr_t)x & 15) == 0 && ((uintptr_t)codes & 15) == 0;
+  // chained slabs: equal slabs of whole steps, a whole number of slabs per plane
+  const uint64_t slab_len = a.nblocks % a.nslabs == 0 ? (uint64_t)(a.nblocks / a.nslabs) * kSlabBlock : 0;
+  if (vec && nz >= 2 && n % kSlabBlock == 0 && slab_len && slab_len % kLzStep == 0 && a.plane % slab_len == 0) {
+    LzArgs c = a;
+    c.rep_shift = 0;  // a 16 KiB window per sub-group, as the plain kernel's
+    while (c.rep_shift < 4 && A * (2u << c.rep_shift) * 4u <= (16u << 10)) ++c.rep_shift;
+    const size_t hist_words = (A * (1u << c.rep_shift) + 3) & ~3u;
+    const size_t ring_words = c.ring_mask ? c.ring_mask + 1 : 0;
+    const size_t lds_chain = (kChain * (hist_words + ring_words) + (kChain - 1) * (size_t)kLzStep) * 4;
+    if (lds_chain <= (160u << 10)) {
+      const uint32_t D = (uint32_t)(a.plane / slab_len);
+      const uint32_t grid = D * ((nz + kChain - 1) / kChain);
+      (void)hipFuncSetAttribute((const void*)lorenzo_chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_chain);
+      timer.before(stream);
+      lorenzo_chain_kernel<<<grid, kChainThreads, lds_chain, stream>>>(c, D, (uint32_t)slab_len, nz);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      timer.after(stream);
+      if (slab_hist) return launch_slab_hist_reduce(slab_hist, nslabs, A, hist, stream);
+      return hipSuccess;
+    }
+  }
+  const size_t lds = lorenzo_lds_bytes(ny, nx, radius);
   const void* fn = vec ? (const void*)lorenzo_hist_kernel<true> : (const void*)lorenzo_hist_kernel<false>;
   if (lds > (64u << 10)) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   timer.before(stream);

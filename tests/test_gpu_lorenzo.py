@@ -7,7 +7,8 @@ sides, so it decides the same integers.  Shapes cover the vector path
 (nx % 8 == 0, aligned), the element path (odd rows, misaligned buffers),
 1D and 2D fields, fields with one row per plane, the longest row the LDS
 ring takes, many slabs with ragged ends, radii from 1 to 8192, IEEE special
-values, the empty field, and the full 512^3 benchmark field.  The encoder
+values, the empty field, chained slabs (four slabs one plane apart per
+workgroup, short last chains), and the full 512^3 benchmark field.  The encoder
 fed with the fused per-slab counts must produce the very stream the plain
 histogram path produces, and that stream must decode to the oracle's codes.
 """
@@ -81,6 +82,26 @@ def test_shapes_match_oracle(shape, nslabs):
     eb = 1e-3 * max(float(x.max() - x.min()), 1.0)
     check(x, _inv(eb), 512, nslabs)
     check(x, _inv(eb), 512, 0)  # no per-slab counts: global atomics
+
+
+# Equal slabs of whole 2048-value steps that tile the planes take the chained
+# kernel (four slabs one plane apart per workgroup, plane-back values passed
+# in LDS); the last chain is short when the plane count is not a multiple of 4.
+CHAINS = [
+    ((7, 64, 128), 14, 512),   # 2 slabs per plane, 2 chains, the second with 3 planes
+    ((7, 64, 128), 7, 512),    # 1 slab per plane
+    ((9, 32, 256), 18, 512),   # last chain of a single plane
+    ((4, 8, 512), 4, 512),     # exactly one chain
+    ((6, 32, 256), 12, 2048),  # alphabet 4096
+    ((7, 64, 128), 0, 512),    # no per-slab counts: counts added with atomics
+]
+
+
+@pytest.mark.parametrize("shape,nslabs,radius", CHAINS)
+def test_chained_slabs_match_oracle(shape, nslabs, radius):
+    x = W.random_field(shape, seed=sum(shape) + nslabs, noise_rel_std=0.02)
+    eb = 1e-3 * float(x.max() - x.min())
+    check(x, _inv(eb), radius, nslabs)
 
 
 @pytest.mark.parametrize("radius", [1, 2, 3, 64, 2048])
