@@ -39,14 +39,15 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
-    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend"),
+    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend", "paperformat"),
                    default="pipeline",
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
                         "serve: a Poisson trace of requests, continuous batching vs one request at a time; "
                         "decode: hf_decode of the workload's encoded stream; "
                         "frontend: from the 512^3 float field, fused quantization + Lorenzo + histogram, "
-                        "then codebook and encode")
+                        "then codebook and encode; "
+                        "paperformat: the paper's ReduceShuffleMerge<M,r> format, swept over M x r (Table 3's shape)")
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     p.add_argument("--rho", default="0.5,0.8",
                    help="serve mode: offered loads as fractions of the measured saturated capacity")
@@ -620,6 +621,109 @@ def run_frontend(args):
     }
 
 
+def run_paperformat(args):
+    """The paper's own format (hf_encode_paper) on the workload's resident
+    codes with the book the main path builds, swept over M in {10, 11, 12}
+    and r in {2, 3, 4} (the grid of Table 3): GB/s of input symbols per call
+    (its three kernels) and the share of symbols left to the side channel.
+    The line's value is M = 10, r = 3, the paper's best cell.  The CPU
+    baseline is the format's oracle on the first chunks."""
+    import torch
+
+    from oracle import paper_format as pf
+    from paper_2010_10039_amd import hf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    spec = workloads.WORKLOADS[args.workload]
+    A = spec["alphabet"]
+    x = workloads.make(args.workload)
+    sb = x.dtype.itemsize
+    d = torch.from_numpy(x.view(np.int16) if sb == 2 else x).cuda()
+    n = x.size
+    enc = hf.Encoder(n, A, args.chunk, args.reduce_log2)
+    enc.run(d)
+    torch.cuda.synchronize()
+    hf.raise_on_status(enc.status, "codebook")
+    status = hf.new_status()
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    grid = {}
+    best = None
+    for M in (10, 11, 12):
+        for r in (2, 3, 4):
+            offs = torch.empty(((n + (1 << M) - 1) >> M) + 1, dtype=torch.int64, device="cuda")
+            bg = torch.empty((n + (1 << r) - 1) >> r, dtype=torch.int64, device="cuda")
+            bs = torch.empty(bg.numel() << r, dtype=d.dtype, device="cuda")
+            nb = torch.empty(1, dtype=torch.int64, device="cuda")
+            ws = torch.empty(hf.hf_paper_workspace_bytes(n, M), dtype=torch.uint8, device="cuda")
+
+            def call(_k=None, M=M, r=r, offs=offs, bg=bg, bs=bs, nb=nb, ws=ws):
+                hf.hf_encode_paper(d, enc.book, M, r, out, offs, bg, bs, nb, ws, status)
+
+            for _ in range(args.warmup):
+                call()
+            ms = _timed(call, args.steps)
+            hf.raise_on_status(status, f"paper format M={M} r={r}")
+            nbreak = int(nb.item())
+            words = int(offs[-1].item())
+            gbs = n * sb / (ms * 1e-3) / 1e9
+            grid[f"M{M}_r{r}"] = {"GBps": round(gbs, 1), "us": round(ms * 1e3, 1),
+                                  "breaking_pct": round(100.0 * nbreak * (1 << r) / n, 5), "words": words}
+            log(f"paper format M={M} r={r}: {ms * 1e3:.1f} us, {gbs:.1f} GB/s, "
+                f"breaking {100.0 * nbreak * (1 << r) / n:.4f}% of symbols")
+            if M == 10 and r == 3:
+                best = (ms, gbs, words, nbreak)
+    ms, gbs, words, nbreak = best
+    # untimed check of the best cell on sampled chunks against the oracle
+    M, r = 10, 3
+    offs = torch.empty(((n + 1023) >> 10) + 1, dtype=torch.int64, device="cuda")
+    res = hf.hf_encode_paper(d, enc.book, M, r, out, offs, status=status)
+    torch.cuda.synchronize()
+    hf.raise_on_status(status, "check")
+    cl = enc.book.cl.cpu().numpy()
+    cw = enc.book.cw.cpu().numpy().view(np.uint64)
+    o = offs.cpu().numpy().view(np.uint64)
+    for k in (0, 1000, ((n + 1023) >> 10) - 1):
+        w, oo, _, _ = pf.encode(x[k << 10:(k + 1) << 10], cl, cw, M, r)
+        if not np.array_equal(out[int(o[k]):int(o[k + 1])].cpu().numpy().view(np.uint32), w):
+            raise SystemExit(f"paper-format chunk {k} differs from the oracle")
+    del res
+    cpu = None
+    if args.cpu_seconds > 0:
+        cnt, t_cpu = 1 << 16, 0.0
+        while True:
+            t0 = time.perf_counter()
+            pf.encode(x[:cnt], cl, cw, M, r)
+            t_cpu = time.perf_counter() - t0
+            if t_cpu > args.cpu_seconds / 3 or cnt >= n:
+                break
+            cnt *= 2
+        cpu = {"value": round(cnt * sb / t_cpu / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the format's Python oracle on the first {cnt} symbols, M=10 r=3, {t_cpu:.2f} s"}
+    alg = n * sb + words * 4 + (((n + 1023) >> 10) + 1) * 8 + nbreak * (8 + (sb << r))
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {
+        "metric": "paper-format encode GB/s of input symbols (M=10, r=3)",
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16" if sb == 2 else "u8",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_symbols": n, "alphabet": A, "M": 10, "r": 3, "grid": grid},
+        "roofline": {"bound": "hbm", "kernel": "pf_count_kernel + pf_scan_kernel + pf_write_kernel",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": alg,
+                     "avg_launch_us": round(ms * 1e3, 2)},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -637,6 +741,9 @@ def main():
         return
     if args.mode == "frontend":
         print(json.dumps(run_frontend(args)), flush=True)
+        return
+    if args.mode == "paperformat":
+        print(json.dumps(run_paperformat(args)), flush=True)
         return
 
     import torch

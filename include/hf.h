@@ -150,6 +150,32 @@ hf_status hf_lorenzo_histogram(const float* d_field, uint32_t nz, uint32_t ny, u
                                uint32_t* d_slab_hist, void* stream);
 
 /*
+ * The paper's own output format, kept as an ablation beside hf_encode's
+ * exact dense stream (Sec. 4.3, Interface ReduceShuffleMerge<M, r>;
+ * Sec. 5.2.2 and Table 3).  Chunks of 2^M symbols (chunk_log2 = M in
+ * [8, 12]) are cut into groups of 2^r symbols (reduce_log2 = r in [1, 5]).
+ * A group's codes, merged MSB first, form one word when they total at most
+ * 32 bits; a group needing more is "breaking": it is left out of the stream
+ * and recorded in a side channel, its global group index in
+ * d_break_groups (uint64, ascending) and its 2^r raw symbols (zero padded
+ * when the last group is short) in d_break_syms (the symbol type).  A
+ * chunk's stream is the concatenation of its non-breaking group words,
+ * padded to a whole 32-bit word; chunks follow one another, chunk k
+ * starting at word d_chunk_word_offsets[k] (uint64[nchunks + 1], total
+ * words at [nchunks]).  *d_nbreak (uint64) receives the number of breaking
+ * groups.  Output beyond out_capacity_words words or break_capacity groups
+ * is not written and raises HF_ERR_CAPACITY; a symbol outside the alphabet
+ * or without a code raises HF_ERR_SYMBOL.  Workspace:
+ * hf_paper_workspace_bytes(n, chunk_log2).
+ */
+size_t hf_paper_workspace_bytes(uint64_t n, uint32_t chunk_log2);
+hf_status hf_encode_paper(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                          uint32_t chunk_log2, uint32_t reduce_log2, uint32_t* d_out, uint64_t out_capacity_words,
+                          uint64_t* d_chunk_word_offsets, uint64_t* d_break_groups, void* d_break_syms,
+                          uint64_t break_capacity, uint64_t* d_nbreak, void* d_ws, size_t ws_bytes,
+                          uint32_t* d_status, void* stream);
+
+/*
  * Stages 2 and 3, codebook construction and canonization (Sec. 4.2,
  * Algorithm 1): from d_hist (uint32[book->alphabet]) fill every array of
  * *book (see hf_codebook).  Leaves are sorted by (count, symbol); code

@@ -197,6 +197,31 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
                                          d_ws, d_status, (hipStream_t)stream, timer));
 }
 
+size_t hf_paper_workspace_bytes(uint64_t n, uint32_t chunk_log2) {
+  if (chunk_log2 < 8 || chunk_log2 > 12) return 0;
+  return hf::paper_workspace_bytes(n, chunk_log2);
+}
+
+hf_status hf_encode_paper(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                          uint32_t chunk_log2, uint32_t reduce_log2, uint32_t* d_out, uint64_t out_capacity_words,
+                          uint64_t* d_chunk_word_offsets, uint64_t* d_break_groups, void* d_break_syms,
+                          uint64_t break_capacity, uint64_t* d_nbreak, void* d_ws, size_t ws_bytes,
+                          uint32_t* d_status, void* stream) {
+  const KernelTimer timer = take_timer();
+  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !d_chunk_word_offsets || !d_nbreak ||
+      !d_status || (n > 0 && (!d_sym || !d_out)))
+    return HF_ERR_ARG;
+  if (chunk_log2 < 8 || chunk_log2 > 12 || reduce_log2 < 1 || reduce_log2 > 5) return HF_ERR_ARG;
+  if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
+  if (break_capacity > 0 && (!d_break_groups || !d_break_syms)) return HF_ERR_ARG;
+  if (n > 0 && (!d_ws || ws_bytes < hf::paper_workspace_bytes(n, chunk_log2) || ((uintptr_t)d_ws & 255)))
+    return HF_ERR_WORKSPACE;
+  return launch_result(hf::launch_encode_paper(d_sym, n, sym_bytes, *book, chunk_log2, reduce_log2, d_out,
+                                               out_capacity_words, d_chunk_word_offsets, d_break_groups,
+                                               d_break_syms, break_capacity, d_nbreak, d_ws, d_status,
+                                               (hipStream_t)stream, timer));
+}
+
 size_t hf_decode_workspace_bytes(void) { return hf::decode_workspace_bytes(); }
 
 hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, uint64_t n, uint32_t sym_bytes,

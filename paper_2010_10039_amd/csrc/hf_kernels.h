@@ -68,6 +68,14 @@ hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, ui
                                     uint16_t* codes, uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist,
                                     int num_cus, hipStream_t stream, const KernelTimer& timer);
 
+// The paper's own format (ReduceShuffleMerge<M, r> words, breaking groups
+// in a side channel, word-aligned chunks): workspace and launch.
+size_t paper_workspace_bytes(uint64_t n, uint32_t chunk_log2);
+hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
+                               uint32_t M, uint32_t r, uint32_t* out, uint64_t cap_words, uint64_t* offsets,
+                               uint64_t* brk_groups, void* brk_syms, uint64_t brk_cap, uint64_t* nbreak, void* ws,
+                               uint32_t* status, hipStream_t stream, const KernelTimer& timer);
+
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.
 size_t codebook_workspace_bytes(uint32_t alphabet);

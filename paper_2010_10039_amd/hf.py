@@ -77,6 +77,11 @@ _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_cod
 _lib.hf_decode_check.restype = ctypes.c_int
 _lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P]
 _lib.hf_lorenzo_histogram.restype = ctypes.c_int
+_lib.hf_paper_workspace_bytes.argtypes = [_U64, _U32]
+_lib.hf_paper_workspace_bytes.restype = _SZ
+_lib.hf_encode_paper.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _P, _U64, _P, _P, _P,
+                                 _U64, _P, _P, _SZ, _P, _P]
+_lib.hf_encode_paper.restype = ctypes.c_int
 _lib.hf_decode_workspace_bytes.argtypes = []
 _lib.hf_decode_workspace_bytes.restype = _SZ
 _lib.hf_decode.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _SZ, _P, _P]
@@ -288,6 +293,44 @@ def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor,
                                 _ptr(sym), _ptr(result), _ptr(ws), 0 if ws is None else ws.numel(),
                                 _ptr(status), _stream()), "hf_decode_check")
     return result
+
+
+def hf_paper_workspace_bytes(n: int, chunk_log2: int) -> int:
+    return int(_lib.hf_paper_workspace_bytes(n, chunk_log2))
+
+
+def hf_encode_paper(sym: torch.Tensor, book: Codebook, chunk_log2: int, reduce_log2: int,
+                    out: torch.Tensor | None = None, offsets: torch.Tensor | None = None,
+                    break_groups: torch.Tensor | None = None, break_syms: torch.Tensor | None = None,
+                    nbreak: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None):
+    """The paper's format (include/hf.h, hf_encode_paper).  Returns (words,
+    chunk word offsets, breaking group indices, their symbols, count), all
+    device tensors; the side channel holds break_groups.numel() groups."""
+    sb = _sym_bytes(sym)
+    n = sym.numel()
+    nch = (n + (1 << chunk_log2) - 1) >> chunk_log2
+    dev = sym.device
+    if out is None:
+        out = torch.empty(max(1, n), dtype=torch.int32, device=dev)  # at most 32 bits a symbol
+    if offsets is None:
+        offsets = torch.empty(nch + 1, dtype=torch.int64, device=dev)
+    if break_groups is None:
+        break_groups = torch.empty(max(1, (n + (1 << reduce_log2) - 1) >> reduce_log2), dtype=torch.int64,
+                                   device=dev)
+    if break_syms is None:
+        break_syms = torch.empty(break_groups.numel() << reduce_log2, dtype=sym.dtype, device=dev)
+    if nbreak is None:
+        nbreak = torch.empty(1, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = torch.empty(max(256, hf_paper_workspace_bytes(n, chunk_log2)), dtype=torch.uint8, device=dev)
+    if status is None:
+        status = new_status(dev)
+    s = book.struct()
+    _check(_lib.hf_encode_paper(_ptr(sym), n, sb, ctypes.byref(s), chunk_log2, reduce_log2, _ptr(out), out.numel(),
+                                _ptr(offsets), _ptr(break_groups), _ptr(break_syms), break_groups.numel(),
+                                _ptr(nbreak), _ptr(ws), ws.numel(), _ptr(status), _stream()), "hf_encode_paper")
+    return out, offsets, break_groups, break_syms, nbreak
 
 
 def hf_decode_workspace_bytes() -> int:

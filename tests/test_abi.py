@@ -139,6 +139,26 @@ def test_front_end_argument_checks(lib):
     assert call(sh=sh, s=4, radius=4096) == 1                              # alphabet 8192 > 4096 with slabs
 
 
+def test_paper_format_argument_checks(lib):
+    P = ctypes.c_void_p
+    U32, U64, SZ = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    f = lib.hf_encode_paper
+    f.argtypes = [P, U64, U32, ctypes.POINTER(_Book), U32, U32, P, U64, P, P, P, U64, P, P, SZ, P, P]
+    lib.hf_paper_workspace_bytes.argtypes = [U64, U32]
+    lib.hf_paper_workspace_bytes.restype = SZ
+    need = lib.hf_paper_workspace_bytes(100000, 10)
+    assert need >= ((100000 + 1023) // 1024) * 16 and lib.hf_paper_workspace_bytes(100000, 13) == 0
+    d, ws = P(0x1000), P(0x100000)
+    book = _Book(1024, *([0x2000] * 6))
+
+    def call(M=10, r=3, sb=2, cap=10, bg=d, bs=d, w=ws, nbytes=need, sym=d):
+        return f(sym, 100000, sb, ctypes.byref(book), M, r, d, 100000, d, bg, bs, cap, d, w, nbytes, d, None)
+
+    assert call(M=7) == 1 and call(M=13) == 1 and call(r=0) == 1 and call(r=6) == 1
+    assert call(sb=3) == 1 and call(sym=P(0x1001)) == 1 and call(bg=None) == 1 and call(bs=None) == 1
+    assert call(w=None) == 2 and call(nbytes=need - 1) == 2 and call(w=P(0x100010)) == 2
+
+
 def test_slab_count_bounds(lib):
     lib.hf_slab_count.restype = ctypes.c_uint32
     lib.hf_slab_count.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
