@@ -7,8 +7,10 @@ the usual SZ/cuSZ recipe, read as:
 
 1. prequantization: d = rint(x * r) in float32, where r is the float32
    factor 1 / (2 eb) for an absolute error bound eb; rint rounds ties to
-   even; the result is clamped to [-2^24, 2^24] with C's fmax / fmin, whose
-   rule (a NaN operand yields the other operand) sends NaN to -2^24;
+   even; the result is clamped to [-2^24, 2^24], which keeps every residual
+   inside 32 bits.  A non-finite value (NaN or an infinity) is outside the
+   domain of an error-bounded quantizer -- no finite reconstruction lies
+   within eb of it -- so a field holding one is refused (NonFiniteInput);
 2. 3D Lorenzo prediction: the residual e is the mixed first difference of d
    along all three axes, with d taken as 0 outside the grid;
 3. codes: q = e + radius when 1 <= e + radius <= 2 radius - 1, else 0 (the
@@ -31,12 +33,20 @@ CLAMP = float(1 << 24)
 SLAB_BLOCK = 4096
 
 
+class NonFiniteInput(ValueError):
+    """The field holds a NaN or an infinity, which no error bound covers."""
+
+
 def prequantize(x: np.ndarray, inv_2eb: float) -> np.ndarray:
-    """Step 1: d = rint(x * r) computed in float32, then fmin(fmax(d, -2^24),
-    2^24) with NaN-ignoring fmax / fmin (NaN -> -2^24); int64."""
-    v = np.asarray(x, dtype=np.float32) * np.float32(inv_2eb)  # one correctly rounded float32 product
-    v = np.rint(v)                                             # ties to even
-    v = np.fmin(np.fmax(v, np.float32(-CLAMP)), np.float32(CLAMP))
+    """Step 1: d = rint(x * r) computed in float32, then clamped to
+    [-2^24, 2^24]; int64.  Raises NonFiniteInput if any x is NaN or infinite."""
+    x = np.asarray(x, dtype=np.float32)
+    if not np.all(np.isfinite(x)):
+        raise NonFiniteInput(f"{int(np.count_nonzero(~np.isfinite(x)))} non-finite value(s) in the field")
+    with np.errstate(over="ignore"):
+        v = x * np.float32(inv_2eb)  # one correctly rounded float32 product (may overflow to +-inf)
+    v = np.rint(v)                   # ties to even
+    v = np.minimum(np.maximum(v, np.float32(-CLAMP)), np.float32(CLAMP))
     return v.astype(np.int64)
 
 

@@ -3,8 +3,10 @@ that do not come from the oracle itself.
 
 - Prequantization: values that are exact multiples of 2 eb (a power-of-two
   bound, so every product is exact) give their multiple; exact half-way
-  values round to the even neighbour; infinities and huge values clamp to
-  +-2^24 and NaN to -2^24 (C's fmax / fmin ignore a NaN operand).
+  values round to the even neighbour; huge finite values clamp to +-2^24;
+  a field holding a NaN or an infinity is refused (no error bound covers a
+  non-finite value).
+- A 2x2x2 field whose codes are derived by hand below.
 - Residual: summing it back along the three axes (the predictor's inverse,
   a 3D prefix sum) recovers the prequantized integers; on tiny grids it
   equals the eight-neighbour inclusion-exclusion sum evaluated point by
@@ -61,11 +63,40 @@ def test_prequantize_rounding_error_at_most_half():
     assert np.all(np.abs(exact - d) <= 0.5 + np.abs(exact) * 2.0 ** -24)
 
 
-def test_prequantize_specials_clamp():
-    # C99 fmax / fmin return the other operand when one is NaN, so NaN
-    # clamps to the lower bound
-    x = np.float32([1e30, -1e30, np.inf, -np.inf, np.nan, 16777216.0 * 4, -0.0])
-    assert list(lz.prequantize(x, 1.0)) == [1 << 24, -(1 << 24), 1 << 24, -(1 << 24), -(1 << 24), 1 << 24, 0]
+def test_prequantize_huge_values_clamp():
+    x = np.float32([1e30, -1e30, 16777216.0 * 4, -16777216.0 * 4, 3e38, -0.0])
+    # 3e38 * 4 overflows the float32 product to +inf, which clamps like any huge value
+    assert list(lz.prequantize(x, 4.0)) == [1 << 24, -(1 << 24), 1 << 24, -(1 << 24), 1 << 24, 0]
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_non_finite_values_are_rejected(bad):
+    x = np.zeros((2, 3, 4), dtype=np.float32)
+    x[1, 2, 3] = bad
+    with pytest.raises(lz.NonFiniteInput):
+        lz.prequantize(x, 1.0)
+    with pytest.raises(lz.NonFiniteInput):
+        lz.lorenzo_codes(x, 1.0, 8)
+
+
+def test_hand_derived_2x2x2():
+    # x[i, j, k] with 2 eb = 1 (r = 1): rint gives d = 1 4 / 2 8 / 3 5 / 7 20
+    # (2.5 -> 2, 7.5 -> 8 and 19.5 -> 20 are ties to even).  Residual
+    # e = sum over (a, b, c) in {0, 1}^3 of (-1)^(a + b + c) d[i - a, j - b, k - c]:
+    #   e000 = 1                          e001 = 4 - 1 = 3
+    #   e010 = 2 - 1 = 1                  e011 = 8 - 2 - 4 + 1 = 3
+    #   e100 = 3 - 1 = 2                  e101 = 5 - 3 - 4 + 1 = -1
+    #   e110 = 7 - 3 - 2 + 1 = 3          e111 = 20 - 7 - 5 - 8 + 3 + 2 + 4 - 1 = 8
+    # radius 4: code = e + 4 inside [1, 7], else 0; e111 + 4 = 12 is an outlier.
+    x = np.float32([[[0.6, 4.4], [2.5, 7.5]], [[2.75, 5.0], [7.25, 19.5]]])
+    assert np.array_equal(lz.prequantize(x, 1.0).reshape(-1), [1, 4, 2, 8, 3, 5, 7, 20])
+    assert np.array_equal(lz.lorenzo_residual(lz.prequantize(x, 1.0)).reshape(-1), [1, 3, 1, 3, 2, -1, 3, 8])
+    assert np.array_equal(lz.lorenzo_codes(x, 1.0, 4), [5, 7, 5, 7, 6, 3, 7, 0])
+    # one NaN anywhere refuses the whole field
+    y = x.copy()
+    y[0, 1, 0] = np.nan
+    with pytest.raises(lz.NonFiniteInput):
+        lz.lorenzo_codes(y, 1.0, 4)
 
 
 # -- residual ----------------------------------------------------------------
