@@ -531,7 +531,7 @@ def run_frontend(args):
     def step(timer=None):
         if timer is not None:
             hf.hf_time_next_main_kernel(*timer)
-        hf.hf_lorenzo_histogram(xd, (dim, dim, dim), inv, radius, codes, hist, S, sh)
+        hf.hf_lorenzo_histogram(xd, (dim, dim, dim), inv, radius, codes, hist, S, sh, status)
         hf.hf_build_codebook(hist, book, ws, status)
         hf.hf_encode(codes, book, chunk, args.reduce_log2, out, offs, ws, status, S, sh)
 

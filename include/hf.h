@@ -46,7 +46,8 @@ typedef enum {
   HF_ERR_CODELEN = 18,   /* a code longer than 64 bits (device; unreachable for n < 2^32) */
   HF_ERR_MISMATCH = 19,  /* hf_decode_check found a difference (device) */
   HF_ERR_INTERNAL = 20,  /* a bounded wait or loop hit its limit (device; a bug guard) */
-  HF_ERR_STREAM = 21     /* hf_decode: a chunk does not decode with the codebook (device) */
+  HF_ERR_STREAM = 21,    /* hf_decode: a chunk does not decode with the codebook (device) */
+  HF_ERR_VALUE = 22      /* hf_lorenzo_histogram: a value of the field is NaN or infinite (device) */
 } hf_status;
 
 #define HF_MAX_CODELEN 64
@@ -127,9 +128,9 @@ hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32
  * field), so that stage 1 needs no pass of its own over the codes.
  * d_field is float32[nz][ny][nx] in C order (flat index
  * f = (i * ny + j) * nx + k); n = nz * ny * nx < 2^32.  For every element:
- *   d = fminf(fmaxf(rint(x * inv_2eb), -2^24), 2^24) in float32 (rint
- *       ties to even; fmaxf / fminf ignore a NaN operand, so NaN gives
- *       -2^24) -- inv_2eb is 1 / (2 eb) for an absolute error bound eb;
+ *   d = rint(x * inv_2eb) in float32 (ties to even), clamped to
+ *       [-2^24, 2^24] -- inv_2eb is 1 / (2 eb) for an absolute error bound
+ *       eb;
  *   e = the 3D Lorenzo residual of d: the mixed first difference along the
  *       three axes, with d = 0 outside the grid (eight neighbours, signs
  *       (-1)^(di + dj + dk));
@@ -141,13 +142,16 @@ hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32
  * for hf_encode.  Requirements (else HF_ERR_ARG): 1 <= radius <= 8192;
  * inv_2eb finite and > 0; nx <= 8192 when ny > 1; d_field 4-byte and d_codes
  * 2-byte aligned (16-byte alignment of both and nx % 8 == 0 take the
- * vector path).  No device errors are possible.  One workgroup per slab
- * streams its part of the field once, re-reads the plane before it (mostly
- * from cache), and keeps the previous row's partial differences in LDS.
+ * vector path); d_status not NULL.  A NaN or an infinity in the field is
+ * outside an error-bounded quantizer's domain (no finite value lies within
+ * eb of it): it raises HF_ERR_VALUE in *d_status, and the codes and counts
+ * are then unspecified.  Workgroups stream their part of the field once
+ * (four slabs one plane apart share their plane-back values when the shape
+ * allows), and keep the previous row's partial differences in LDS.
  */
 hf_status hf_lorenzo_histogram(const float* d_field, uint32_t nz, uint32_t ny, uint32_t nx, float inv_2eb,
                                uint32_t radius, uint16_t* d_codes, uint32_t* d_hist, uint32_t nslabs,
-                               uint32_t* d_slab_hist, void* stream);
+                               uint32_t* d_slab_hist, uint32_t* d_status, void* stream);
 
 /*
  * The paper's own output format, kept as an ablation beside hf_encode's

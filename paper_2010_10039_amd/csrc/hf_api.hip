@@ -125,6 +125,7 @@ const char* hf_status_string(uint32_t code) {
     case HF_ERR_MISMATCH: return "decoded stream differs from the input";
     case HF_ERR_INTERNAL: return "internal bound exceeded";
     case HF_ERR_STREAM: return "stream does not decode with the codebook";
+    case HF_ERR_VALUE: return "a value of the field is NaN or infinite";
     default: return "unknown status";
   }
 }
@@ -153,17 +154,19 @@ hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32
 
 hf_status hf_lorenzo_histogram(const float* d_field, uint32_t nz, uint32_t ny, uint32_t nx, float inv_2eb,
                                uint32_t radius, uint16_t* d_codes, uint32_t* d_hist, uint32_t nslabs,
-                               uint32_t* d_slab_hist, void* stream) {
+                               uint32_t* d_slab_hist, uint32_t* d_status, void* stream) {
   const KernelTimer timer = take_timer();
   const uint64_t n = (uint64_t)nz * ny * nx;
-  if (radius == 0 || radius > 8192u || !d_hist || !isfinite(inv_2eb) || !(inv_2eb > 0.0f)) return HF_ERR_ARG;
+  if (radius == 0 || radius > 8192u || !d_hist || !d_status || !isfinite(inv_2eb) || !(inv_2eb > 0.0f))
+    return HF_ERR_ARG;
   if (n >= (1ull << 32) || (ny > 1 && nx > 8192u)) return HF_ERR_ARG;
   if (n > 0 && (!d_field || !d_codes || ((uintptr_t)d_field & 3) || ((uintptr_t)d_codes & 1))) return HF_ERR_ARG;
   if (d_slab_hist && (nslabs == 0 || nslabs > blocks_of(n) || nslabs > hf::kMaxSlabs ||
                       2 * radius > hf::kSlabHistMaxAlphabet))
     return HF_ERR_ARG;
   return launch_result(hf::launch_lorenzo_histogram(d_field, nz, ny, nx, inv_2eb, radius, d_codes, d_hist,
-                                                    nslabs, d_slab_hist, num_cus(), (hipStream_t)stream, timer));
+                                                    nslabs, d_slab_hist, d_status, num_cus(), (hipStream_t)stream,
+                                                    timer));
 }
 
 hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,

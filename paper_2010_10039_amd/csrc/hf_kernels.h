@@ -66,7 +66,7 @@ hipError_t launch_slab_hist_reduce(const uint32_t* slab_hist, uint32_t nslabs, u
 size_t lorenzo_lds_bytes(uint32_t ny, uint32_t nx, uint32_t radius);
 hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, uint32_t nx, float r, uint32_t radius,
                                     uint16_t* codes, uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist,
-                                    int num_cus, hipStream_t stream, const KernelTimer& timer);
+                                    uint32_t* status, int num_cus, hipStream_t stream, const KernelTimer& timer);
 
 // The paper's own format (ReduceShuffleMerge<M, r> words, breaking groups
 // in a side channel, word-aligned chunks): workspace and launch.

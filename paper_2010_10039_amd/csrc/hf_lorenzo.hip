@@ -76,13 +76,20 @@ struct LzArgs {
   uint32_t ring_mask;  // ring words - 1; 0 when ny == 1 (no row above ever exists)
   uint32_t nslabs;
   uint32_t nblocks;
+  uint32_t* status;    // HF_ERR_VALUE when a value of the field is NaN or infinite
 };
 
-// Prequantization: x * r rounded to the nearest integer, ties to even,
-// clamped to [-2^24, 2^24] by fmaxf / fminf, which pass over a NaN operand
-// (so NaN gives -2^24).
+// Prequantization of a finite value: x * r rounded to the nearest integer,
+// ties to even, clamped to [-2^24, 2^24] (a product that overflows to an
+// infinity clamps too).  Non-finite values are outside the quantizer's
+// domain: the steps below flag them with nonfinite() and the call fails.
 __device__ __forceinline__ int prequant(float x, float r) {
   return (int)fminf(fmaxf(rintf(x * r), -kLzClamp), kLzClamp);
+}
+
+// 1 if x is NaN or an infinity (all exponent bits set).
+__device__ __forceinline__ uint32_t nonfinite(float x) {
+  return (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u ? 1u : 0u;
 }
 
 // u(f) = d(f) - [f >= P] d(f - P)
@@ -144,7 +151,8 @@ __device__ __forceinline__ uint32_t lz_code(const LzArgs& a, int t, int prev) { 
 // writes t to the ring, reads the row above after a barrier, and stores
 // codes and counts.
 __device__ __forceinline__ void vec_step(const LzArgs& a, uint64_t base, uint64_t s_hi, int* ring, char* subr,
-                                         uint32_t hshift, bool lane0, const LzFetch& cur, LzFetch& nxt) {
+                                         uint32_t hshift, bool lane0, const LzFetch& cur, LzFetch& nxt,
+                                         uint32_t& bad) {
   const uint32_t f = (uint32_t)(base + threadIdx.x * kLzVec);
   fetch_step(a, (uint64_t)f + kLzStep, s_hi, nxt);
   // Take all of `cur` here, on every path: the compiler then knows those
@@ -156,7 +164,10 @@ __device__ __forceinline__ void vec_step(const LzArgs& a, uint64_t base, uint64_
   const int mb = f >= a.plane ? -1 : 0;
   int u[kLzVec];
 #pragma unroll
-  for (int e = 0; e < kLzVec; ++e) u[e] = prequant(cur.o[e], a.r) - (prequant(cur.b[e], a.r) & mb);
+  for (int e = 0; e < kLzVec; ++e) {
+    bad |= nonfinite(cur.o[e]);  // the lane's own values (every group of this step is inside the slab)
+    u[e] = prequant(cur.o[e], a.r) - (prequant(cur.b[e], a.r) & mb);
+  }
   const int up = __shfl_up(u[kLzVec - 1], 1, 64);
   const int own_left = prequant(cur.lo, a.r) - (prequant(cur.lb, a.r) & (f - 1 >= a.plane ? -1 : 0));
   const int left = lane0 ? own_left : up;
@@ -195,7 +206,7 @@ __device__ __forceinline__ void vec_step(const LzArgs& a, uint64_t base, uint64_
 // One step element by element (groups that are not whole, unaligned
 // fields): the same three differences from direct loads.
 __device__ __forceinline__ void elem_step(const LzArgs& a, uint64_t base, uint64_t s_hi, int* ring, char* subr,
-                                          uint32_t hshift) {
+                                          uint32_t hshift, uint32_t& bad) {
   const uint64_t f64 = base + threadIdx.x * kLzVec;
   const uint32_t f = (uint32_t)f64;  // meaningful only while f64 < s_hi
   int t[kLzVec];
@@ -204,6 +215,7 @@ __device__ __forceinline__ void elem_step(const LzArgs& a, uint64_t base, uint64
     const bool in = f64 + e < s_hi;
     const uint32_t fe = f + e;
     t[e] = in ? t_at(a, fe) : 0;
+    if (in) bad |= nonfinite(a.x[fe]);
     if (a.ring_mask && in) ring[fe & a.ring_mask] = t[e];
   }
   __syncthreads();
@@ -252,21 +264,23 @@ __global__ __launch_bounds__(kLzThreads) void lorenzo_hist_kernel(LzArgs a) {
   char* const subr = (char*)(sub + (tid & (reps - 1)));
   const uint32_t hshift = a.rep_shift + 2;
   uint64_t base = s_lo;
+  uint32_t bad = 0;
   if (kVec) {
     const uint64_t v_end = s_lo + (s_hi - s_lo) / kLzStep * kLzStep;
     const bool lane0 = (tid & 63) == 0;
     LzFetch va, vb;
     fetch_step(a, s_lo + tid * kLzVec, s_hi, va);
     for (; base + 2 * kLzStep <= v_end; base += 2 * kLzStep) {
-      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb);
-      vec_step(a, base + kLzStep, s_hi, ring, subr, hshift, lane0, vb, va);
+      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb, bad);
+      vec_step(a, base + kLzStep, s_hi, ring, subr, hshift, lane0, vb, va, bad);
     }
     if (base < v_end) {
-      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb);
+      vec_step(a, base, s_hi, ring, subr, hshift, lane0, va, vb, bad);
       base += kLzStep;
     }
   }
-  for (; base < s_hi; base += kLzStep) elem_step(a, base, s_hi, ring, subr, hshift);
+  for (; base < s_hi; base += kLzStep) elem_step(a, base, s_hi, ring, subr, hshift, bad);
+  if (bad) raise_status(a.status, HF_ERR_VALUE);
   __syncthreads();
   if (a.slab_hist) {
     uint32_t* row = a.slab_hist + (uint64_t)g * a.A;
@@ -329,7 +343,7 @@ struct ChainLane {
 // One step of sub-group k at group f64: uses `cur` (fetched two steps
 // earlier) and fetches the step two ahead into `ahead`.
 __device__ __forceinline__ void chain_step(const LzArgs& a, const ChainLane& c, uint64_t f64, const LzFetch& cur,
-                                           LzFetch& ahead) {
+                                           LzFetch& ahead, uint32_t& bad) {
   const uint32_t f = (uint32_t)f64;
   fetch_chain(a, f64 + 2 * kLzStep, c.s_hi, c.first_sub, c.lane0, ahead);
   asm volatile("" ::"v"(cur.o[0]), "v"(cur.o[1]), "v"(cur.o[2]), "v"(cur.o[3]), "v"(cur.o[4]), "v"(cur.o[5]),
@@ -337,7 +351,10 @@ __device__ __forceinline__ void chain_step(const LzArgs& a, const ChainLane& c, 
                "v"(cur.b[4]), "v"(cur.b[5]), "v"(cur.b[6]), "v"(cur.b[7]), "v"(cur.lo), "v"(cur.lb));
   int d[kLzVec];
 #pragma unroll
-  for (int e = 0; e < kLzVec; ++e) d[e] = prequant(cur.o[e], a.r);
+  for (int e = 0; e < kLzVec; ++e) {
+    bad |= c.active ? nonfinite(cur.o[e]) : 0u;  // an inactive sub-group reads index 0, not values of its own
+    d[e] = prequant(cur.o[e], a.r);
+  }
   if (c.publish) {
     int4* w = (int4*)(c.xb_out + c.lt * kLzVec);
     w[0] = make_int4(d[0], d[1], d[2], d[3]);
@@ -441,13 +458,15 @@ __global__ __launch_bounds__(kChainThreads) void lorenzo_chain_kernel(LzArgs a, 
   fetch_chain(a, f0, c.s_hi, c.first_sub, c.lane0, va);
   fetch_chain(a, f0 + kLzStep, c.s_hi, c.first_sub, c.lane0, vb);
   uint32_t st = 0;
+  uint32_t bad = 0;
   for (; st + 3 <= steps; st += 3) {
-    chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc);
-    chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va);
-    chain_step(a, c, f0 + (uint64_t)(st + 2) * kLzStep, vc, vb);
+    chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc, bad);
+    chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va, bad);
+    chain_step(a, c, f0 + (uint64_t)(st + 2) * kLzStep, vc, vb, bad);
   }
-  if (st < steps) chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc);
-  if (st + 1 < steps) chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va);
+  if (st < steps) chain_step(a, c, f0 + (uint64_t)st * kLzStep, va, vc, bad);
+  if (st + 1 < steps) chain_step(a, c, f0 + (uint64_t)(st + 1) * kLzStep, vb, va, bad);
+  if (bad) raise_status(a.status, HF_ERR_VALUE);
   __syncthreads();
   if (!c.active) return;
   if (a.slab_hist) {
@@ -485,7 +504,7 @@ size_t lorenzo_lds_bytes(uint32_t ny, uint32_t nx, uint32_t radius) {
 
 hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, uint32_t nx, float r, uint32_t radius,
                                     uint16_t* codes, uint32_t* hist, uint32_t nslabs, uint32_t* slab_hist,
-                                    int num_cus, hipStream_t stream, const KernelTimer& timer) {
+                                    uint32_t* status, int num_cus, hipStream_t stream, const KernelTimer& timer) {
   const uint64_t n = (uint64_t)nz * ny * nx;
   const uint32_t A = 2 * radius;
   hipError_t e;
@@ -495,6 +514,7 @@ hipError_t launch_lorenzo_histogram(const float* x, uint32_t nz, uint32_t ny, ui
   a.codes = codes;
   a.hist = hist;
   a.slab_hist = slab_hist;
+  a.status = status;
   a.n = (uint32_t)n;
   a.nx = nx;
   a.plane = ny * nx;

@@ -26,6 +26,7 @@ HF_ERR_CODELEN = 18
 HF_ERR_MISMATCH = 19
 HF_ERR_INTERNAL = 20
 HF_ERR_STREAM = 21
+HF_ERR_VALUE = 22
 MAX_CODELEN = 64
 
 if not os.path.exists(_LIB_PATH):
@@ -75,7 +76,7 @@ _lib.hf_encode.restype = ctypes.c_int
 _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
                                  _SZ, _P, _P]
 _lib.hf_decode_check.restype = ctypes.c_int
-_lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P]
+_lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P, _P]
 _lib.hf_lorenzo_histogram.restype = ctypes.c_int
 _lib.hf_paper_workspace_bytes.argtypes = [_U64, _U32]
 _lib.hf_paper_workspace_bytes.restype = _SZ
@@ -222,11 +223,13 @@ def hf_histogram(sym: torch.Tensor, alphabet: int, hist: torch.Tensor | None = N
 
 def hf_lorenzo_histogram(field: torch.Tensor, dims, inv_2eb: float, radius: int,
                          codes: torch.Tensor | None = None, hist: torch.Tensor | None = None,
-                         nslabs: int = 0, slab_hist: torch.Tensor | None = None):
+                         nslabs: int = 0, slab_hist: torch.Tensor | None = None,
+                         status: torch.Tensor | None = None):
     """Quantization codes (int16 tensor holding uint16) of the float32 field
     of shape dims = (nz, ny, nx) and their histogram (int32[2 radius]); with
     `slab_hist` (int32[nslabs * 2 radius]) also the per-slab counts for
-    hf_encode.  Returns (codes, hist)."""
+    hf_encode.  A NaN or infinite value raises HF_ERR_VALUE in `status`.
+    Returns (codes, hist)."""
     if field.dtype != torch.float32 or not field.is_contiguous():
         raise TypeError("the field must be a contiguous float32 tensor")
     nz, ny, nx = (int(v) for v in dims)
@@ -236,8 +239,10 @@ def hf_lorenzo_histogram(field: torch.Tensor, dims, inv_2eb: float, radius: int,
         codes = torch.empty(field.numel(), dtype=torch.int16, device=field.device)
     if hist is None:
         hist = torch.empty(2 * radius, dtype=torch.int32, device=field.device)
+    if status is None:
+        status = new_status(field.device)
     _check(_lib.hf_lorenzo_histogram(_ptr(field), nz, ny, nx, float(inv_2eb), radius, _ptr(codes), _ptr(hist),
-                                     nslabs, _ptr(slab_hist), _stream()), "hf_lorenzo_histogram")
+                                     nslabs, _ptr(slab_hist), _ptr(status), _stream()), "hf_lorenzo_histogram")
     return codes, hist
 
 

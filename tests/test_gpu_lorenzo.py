@@ -6,8 +6,9 @@ bit-exact.  The float step (prequantization) is taken in float32 on both
 sides, so it decides the same integers.  Shapes cover the vector path
 (nx % 8 == 0, aligned), the element path (odd rows, misaligned buffers),
 1D and 2D fields, fields with one row per plane, the longest row the LDS
-ring takes, many slabs with ragged ends, radii from 1 to 8192, IEEE special
-values, the empty field, chained slabs (four slabs one plane apart per
+ring takes, many slabs with ragged ends, radii from 1 to 8192, huge finite
+values, exact ties, non-finite values (refused with HF_ERR_VALUE on every
+path, as the oracle refuses them), the empty field, chained slabs (four slabs one plane apart per
 workgroup, short last chains), and the full 512^3 benchmark field.  The encoder
 fed with the fused per-slab counts must produce the very stream the plain
 histogram path produces, and that stream must decode to the oracle's codes.
@@ -44,8 +45,10 @@ def run_gpu(x: np.ndarray, inv: float, radius: int, nslabs: int = 0, x_off: int 
     cd = cb[c_off:]
     hist = torch.full((A,), -1, dtype=torch.int32, device="cuda")
     sh = torch.full((max(1, nslabs) * A,), -1, dtype=torch.int32, device="cuda") if nslabs else None
-    hf.hf_lorenzo_histogram(xd, (nz, ny, nx), inv, radius, cd, hist, nslabs, sh)
+    status = hf.new_status()
+    hf.hf_lorenzo_histogram(xd, (nz, ny, nx), inv, radius, cd, hist, nslabs, sh, status)
     torch.cuda.synchronize()
+    assert hf.read_status(status) == hf.HF_OK
     codes = cd.cpu().numpy().view(np.uint16)
     h = hist.cpu().numpy().view(np.uint32)
     rows = sh.cpu().numpy().view(np.uint32).reshape(nslabs, A) if nslabs else None
@@ -128,19 +131,43 @@ def test_misaligned_buffers(x_off, c_off):
     check(x, _inv(eb), 512, nslabs=2, x_off=x_off, c_off=c_off)
 
 
-def test_special_values_and_ties():
+def test_huge_values_and_ties():
     rng = np.random.default_rng(9)
     x = rng.normal(0, 3, size=(4, 8, 64)).astype(np.float32)
     flat = x.reshape(-1)
-    flat[::97] = np.nan
-    flat[5::101] = np.inf
-    flat[7::103] = -np.inf
     flat[11::89] = 1e30
     flat[13::83] = -1e30
+    flat[17::79] = 3e38  # the float32 product overflows to +inf and clamps
     k = rng.integers(-50, 50, size=flat.size // 7)
     flat[1::7][: k.size] = ((k + 0.5) / 4.0).astype(np.float32)  # exact ties at inv = 4
     check(x, 4.0, 512, nslabs=1)
     check(x, 4.0, 8, nslabs=1)
+
+
+# (shape, nslabs, where): the vector path, the element path (odd rows), the
+# chained path (equal slabs tiling the planes), and the unchained vector path
+# without per-slab counts; `where` puts the one bad value first, inside, or
+# last in the field.
+@pytest.mark.parametrize("shape,nslabs", [((4, 8, 64), 1), ((3, 5, 37), 1), ((8, 32, 256), 16), ((4, 24, 512), 0)])
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_non_finite_values_are_refused(shape, nslabs, bad, where):
+    """The oracle refuses a field holding a NaN or an infinity
+    (lorenzo.NonFiniteInput); the kernel must raise HF_ERR_VALUE."""
+    x = W.random_field(shape, seed=3)
+    flat = x.reshape(-1)
+    flat[{"first": 0, "middle": flat.size // 2 + 3, "last": flat.size - 1}[where]] = bad
+    inv = _inv(1e-3 * float(np.nanmax(x[np.isfinite(x)]) - np.nanmin(x[np.isfinite(x)])))
+    with pytest.raises(lz.NonFiniteInput):
+        lz.lorenzo_codes(x, inv, 512)
+    A = 1024
+    xd = torch.from_numpy(flat).cuda()
+    cd = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    hist = torch.empty(A, dtype=torch.int32, device="cuda")
+    sh = torch.empty(max(1, nslabs) * A, dtype=torch.int32, device="cuda") if nslabs else None
+    status = hf.new_status()
+    hf.hf_lorenzo_histogram(xd, x.shape, inv, 512, cd, hist, nslabs, sh, status)
+    assert hf.read_status(status) == hf.HF_ERR_VALUE
 
 
 def test_empty_field_zeroes_histogram():
