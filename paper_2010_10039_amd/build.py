@@ -1,7 +1,8 @@
-"""Build libhf.so (HIP for gfx950) in-tree with hipcc.
+"""Build libhf.so (HIP for gfx950) and libhf_cpu.so (OpenMP) in-tree.
 
-Every translation unit under csrc/ is compiled to an object in parallel and
-linked into paper_2010_10039_amd/libhf.so.  Run as
+Every translation unit under csrc/ is compiled with hipcc to an object in
+parallel and linked into paper_2010_10039_amd/libhf.so; cpu/hf_cpu.cpp is
+compiled with g++ -fopenmp into paper_2010_10039_amd/libhf_cpu.so.  Run as
 ``python -m paper_2010_10039_amd.build``.
 """
 from __future__ import annotations
@@ -18,6 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhf.so")
+CPU_SRC = os.path.join(PKG, "cpu", "hf_cpu.cpp")
+CPU_LIB = os.path.join(PKG, "libhf_cpu.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -54,12 +57,29 @@ def _compile(src: str) -> str:
     return obj
 
 
+def build_cpu(verbose: bool = False) -> str:
+    """Compile the multi-core CPU baseline (cpu/hf_cpu.cpp) into libhf_cpu.so."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", f"-I{INCLUDE}",
+           CPU_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed on {CPU_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CPU_LIB)
+    if verbose:
+        print(f"built {CPU_LIB}")
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every csrc/*.hip for gfx950 and link libhf.so; returns its path."""
+    """Compile every csrc/*.hip for gfx950 and link libhf.so (and the CPU
+    baseline library); returns libhf.so's path."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
+        cpu = ex.submit(build_cpu, verbose)
         objs = list(ex.map(_compile, srcs))
+        cpu.result()
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
