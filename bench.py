@@ -39,7 +39,8 @@ def parse():
     p.add_argument("--reduce-log2", type=int, default=0)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
-    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend", "paperformat"),
+    p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend", "paperformat",
+                                      "cpu"),
                    default="pipeline",
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
@@ -120,6 +121,88 @@ def cpu_baseline(x: np.ndarray, A: int, chunk: int, budget_s: float):
         "sample": f"{passes} whole pass(es) of histogram+codebook+encode over the same "
                   f"{x.size} symbols, serial C, {per_pass:.2f} s per pass",
     }
+
+
+def cpu_parallel(x: np.ndarray, A: int, chunk: int, budget_s: float):
+    """The multi-core CPU baseline (libhf_cpu: OpenMP histogram, parallel
+    codebook, chunk-parallel packer; the paper's Table 6 analog) on the same
+    input with every thread OpenMP gives it; median of up to 5 whole passes
+    after one warm-up, per stage and in total."""
+    from paper_2010_10039_amd import hf_cpu
+
+    def one():
+        t0 = time.perf_counter()
+        h = hf_cpu.histogram(x, A)
+        t1 = time.perf_counter()
+        b = hf_cpu.codebook(h)
+        t2 = time.perf_counter()
+        hf_cpu.encode(x, b["cl"], b["cw"], chunk, cap_words=(int(b["info"][2]) + 31) // 32)
+        t3 = time.perf_counter()
+        return t3 - t0, (t1 - t0, t2 - t1, t3 - t2)
+
+    one()
+    runs, spent = [], 0.0
+    while len(runs) < 5 and (not runs or spent < budget_s):
+        tot, parts = one()
+        runs.append((tot, parts))
+        spent += tot
+    runs.sort()
+    tot, parts = runs[len(runs) // 2]
+    return {
+        "value": round(x.nbytes / tot / 1e9, 3),
+        "unit": "GB/s",
+        "cores": hf_cpu.threads(),
+        "kind": "multi-thread CPU (OpenMP histogram, parallel codebook, chunk-parallel pack)",
+        "sample": f"median of {len(runs)} whole passes over the same {x.size} symbols",
+        "stage_ms": {"hist": round(parts[0] * 1e3, 3), "codebook": round(parts[1] * 1e3, 3),
+                     "encode": round(parts[2] * 1e3, 3)},
+    }
+
+
+def run_cpu(args):
+    """The CPU side of the paper's evaluation on this host.  Table 5 analog:
+    codebook build time against alphabet size (synthetic normal histograms,
+    the paper's stand-in for large alphabets) and thread count, beside the
+    serial oracle.  Table 6 analog: histogram and encode GB/s of the
+    multi-thread CPU encoder against thread count on the benchmark's
+    Lorenzo codes."""
+    import oracle
+    from paper_2010_10039_amd import hf_cpu, workloads
+
+    maxt = hf_cpu.threads()
+    counts = sorted({t for t in (1, 2, 4, 8, 16, 32, 64, 128) if t <= maxt} | {maxt})
+
+    def best(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    codebook = []
+    for A in (1024, 2048, 4096, 8192, 16384, 32768, 65536):
+        h = workloads.skewed_histogram(A, 1 << 24, seed=1)
+        row = {"alphabet": A, "used": int(np.count_nonzero(h)),
+               "oracle_serial_ms": round(best(lambda: oracle.codebook(h)) * 1e3, 4)}
+        for t in counts:
+            row[f"t{t}_ms"] = round(best(lambda: hf_cpu.codebook(h, t)) * 1e3, 4)
+        codebook.append(row)
+        log(f"codebook A={A}: " + ", ".join(f"{k}={v}" for k, v in row.items() if k.endswith("_ms")))
+    x = workloads.make(args.workload)
+    A = workloads.WORKLOADS[args.workload]["alphabet"]
+    book = hf_cpu.codebook(hf_cpu.histogram(x, A))
+    cap = (int(book["info"][2]) + 31) // 32
+    enc = []
+    for t in counts:
+        th = best(lambda: hf_cpu.histogram(x, A, t), 3)
+        te = best(lambda: hf_cpu.encode(x, book["cl"], book["cw"], args.chunk, cap, t), 3)
+        enc.append({"threads": t, "hist_gbs": round(x.nbytes / th / 1e9, 3), "encode_gbs": round(x.nbytes / te / 1e9, 3),
+                    "hist_enc_gbs": round(x.nbytes / (th + te) / 1e9, 3)})
+        log(f"threads {t}: " + ", ".join(f"{k}={v}" for k, v in enc[-1].items()))
+    return {"mode": "cpu", "workload": args.workload, "threads_max": maxt, "codebook_table5": codebook,
+            "encoder_table6": enc}
 
 
 def _timed(fn, steps: int):
@@ -750,6 +833,9 @@ def main():
     if args.mode == "paperformat":
         print(json.dumps(run_paperformat(args)), flush=True)
         return
+    if args.mode == "cpu":
+        print(json.dumps(run_cpu(args)), flush=True)
+        return
 
     import torch
 
@@ -868,10 +954,12 @@ def main():
         if t is not None:
             roofline["traffic"] = t["bytes"]
             roofline["traffic_detail"] = t
-    cpu = None
+    cpu = cpu_par = None
     if args.cpu_seconds > 0:
         log("timing the CPU oracle")
         cpu = cpu_baseline(x, A, args.chunk, args.cpu_seconds)
+        log("timing the multi-thread CPU baseline")
+        cpu_par = cpu_parallel(x, A, args.chunk, args.cpu_seconds / 2)
     line = {
         "metric": "end-to-end encode GB/s of input symbols",
         "value": round(value, 2),
@@ -903,6 +991,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
     }
     print(json.dumps(line), flush=True)
 
