@@ -213,7 +213,9 @@ hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, voi
  *                  one extra pass over the input counts bits per slab).
  * The result is bit-identical for every chunk_symbols, reduce_log2 and
  * slab partition.  Raises HF_ERR_SYMBOL for a symbol >= alphabet or with
- * cl == 0, and HF_ERR_CAPACITY when total_bits > 32 * out_capacity_words
+ * cl == 0, or when d_slab_hist does not hold these symbols' per-slab counts
+ * (a slab's bits then differ from its counted total; the stream is
+ * unspecified), and HF_ERR_CAPACITY when total_bits > 32 * out_capacity_words
  * (nothing is written at or past d_out[out_capacity_words]).
  */
 hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,

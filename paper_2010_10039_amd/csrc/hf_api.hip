@@ -105,7 +105,8 @@ uint64_t hf_bound_words(uint64_t n, uint32_t alphabet) {
 }
 
 uint32_t hf_reduction_factor(double beta) {
-  if (!(beta >= 1.0)) beta = 1.0;
+  if (!(beta >= 1.0)) beta = 1.0;   // also NaN
+  if (beta > 64.0) beta = 64.0;      // codes are at most 64 bits (also +inf)
   const int fl = (int)floor(log2(beta));
   int r = 5 - fl - 1;  // floor(log2 beta) + r + 1 = log2(32) = 5
   if (r < hf::kEncMinR) r = hf::kEncMinR;

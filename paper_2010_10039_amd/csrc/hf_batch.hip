@@ -126,21 +126,23 @@ hf_status make_plan(const hf_stream_desc* descs, uint32_t ns, char* ws, uint32_t
     b.out = d.out;
     b.cap_words = d.out_capacity_words;
     b.offsets = d.chunk_bit_offsets;
-    b.status = d_status + s;
-    b.part = (uint32_t*)(ws + o);
+    // when only sizing (ws == NULL) no address is formed
+    auto at = [ws](size_t off) { return ws ? ws + off : (char*)nullptr; };
+    b.status = d_status ? d_status + s : nullptr;
+    b.part = (uint32_t*)at(o);
     o += align256((size_t)b.nslabs * A * 4);
     if (d.hist) {
       b.hist = d.hist;
     } else {
-      b.hist = (uint32_t*)(ws + o);
+      b.hist = (uint32_t*)at(o);
       o += align256((size_t)A * 4);
     }
     const size_t cb = hf::codebook_workspace_bytes(A);
-    b.cb_ws = cb ? ws + o : nullptr;
+    b.cb_ws = cb ? at(o) : nullptr;
     o += align256(cb);
-    b.slab_bits = (uint64_t*)(ws + o);
+    b.slab_bits = (uint64_t*)at(o);
     o += align256((size_t)b.nslabs * 8);
-    b.slab_tail = (uint32_t*)(ws + o);
+    b.slab_tail = (uint32_t*)at(o);
     o += align256((size_t)b.nslabs * 4);
     for (uint32_t g = 0; g < b.nslabs; ++g) p.item_stream.push_back(s);
   }

@@ -228,8 +228,8 @@ struct EncShared {
 };
 
 // `expect` is the slab's bit total from the prepass (sum of count * cl): a
-// table-mode slab whose tiles add up to anything else held a symbol without
-// code or outside the alphabet.
+// slab whose tiles add up to anything else held a symbol without code or
+// outside the alphabet, or came with per-slab counts of other symbols.
 template <int R, int SB, int MODE>
 __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* tab, uint32_t* buf,
                                             uint32_t* dummy, EncShared& sh, uint32_t g, uint64_t G,
@@ -465,8 +465,10 @@ __device__ __forceinline__ void encode_slab(const EncArgs& a, const uint32_t* ta
       sh.tailw = 0;
     }
   }
-  if (kTabMode && tid == 0 && run != expect)
-    raise_status(a.status, HF_ERR_SYMBOL);
+  // every mode: the slab's bits must add up to the prepass's total (else a
+  // symbol had no code, or the per-slab counts were not these symbols' and
+  // later slabs were placed at wrong offsets)
+  if (tid == 0 && run != expect) raise_status(a.status, HF_ERR_SYMBOL);
 }
 
 __device__ __forceinline__ int encode_mode(uint32_t A, uint32_t lmax) {

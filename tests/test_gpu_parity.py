@@ -320,6 +320,28 @@ def test_encode_long_codes(nfib, A, base, mode):
         assert np.all(words[rw.size:] == SENTINEL)
 
 
+@pytest.mark.parametrize("nfib,mode", [(20, "packed table"), (30, "split tables"),
+                                       (33, "codebook from global memory"), (34, "codes over 32 bits")])
+def test_encode_flags_slab_counts_of_other_symbols(nfib, mode):
+    """Per-slab counts that are not the symbols' (here: those of another
+    shuffle of the same multiset, so every slab has the right size but the
+    wrong bits) place later slabs wrongly; every mode must flag it, and
+    nothing may be written past the capacity."""
+    x = _fib_stream(nfib, 200, 1)
+    other = _fib_stream(nfib, 200, 2)
+    A = 1024
+    S = hf.hf_slab_count(x.size, A)
+    assert S >= 2
+    part = np.stack([oracle.histogram(other[lo:hi], A) for lo, hi in slab_ranges(x.size, S)])
+    book, code = gpu_book(oracle.histogram(x, A))
+    assert code == 0
+    rw, _, tb = oracle.encode(x, oracle.codebook(oracle.histogram(x, A)), 4096)
+    cap = rw.size
+    words, offs, code = gpu_encode(x, book, 4096, 4, cap_words=cap, nslabs=S, slab_hist=part)
+    assert code == hf.HF_ERR_SYMBOL, mode
+    assert np.all(words[cap:] == SENTINEL), mode
+
+
 def test_encode_large_alphabet_global_table():
     x = np.clip(np.rint(np.random.default_rng(4).normal(30000, 3000, size=500_001)), 0, 65535).astype(np.uint16)
     check_pipeline(x, 65536, 4096)
