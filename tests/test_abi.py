@@ -121,14 +121,16 @@ def test_front_end_argument_checks(lib):
     P = ctypes.c_void_p
     U32, F = ctypes.c_uint32, ctypes.c_float
     f = lib.hf_lorenzo_histogram
-    f.argtypes = [P, U32, U32, U32, F, U32, P, P, U32, P, P]
-    x, c, h, sh = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
-    ok = dict(x=x, nz=8, ny=16, nx=512, r=100.0, radius=512, c=c, h=h, s=0, sh=None)
+    f.argtypes = [P, U32, U32, U32, F, U32, P, P, U32, P, P, P]
+    x, c, h, sh, st = P(0x10000), P(0x20000), P(0x30000), P(0x40000), P(0x50000)
+    ok = dict(x=x, nz=8, ny=16, nx=512, r=100.0, radius=512, c=c, h=h, s=0, sh=None, st=st)
 
     def call(**kw):
         a = dict(ok, **kw)
-        return f(a["x"], a["nz"], a["ny"], a["nx"], a["r"], a["radius"], a["c"], a["h"], a["s"], a["sh"], None)
+        return f(a["x"], a["nz"], a["ny"], a["nx"], a["r"], a["radius"], a["c"], a["h"], a["s"], a["sh"], a["st"],
+                 None)
 
+    assert call(st=None) == 1                                              # the status word is required
     assert call(radius=0) == 1 and call(radius=8193) == 1
     assert call(r=0.0) == 1 and call(r=-1.0) == 1 and call(r=float("inf")) == 1 and call(r=float("nan")) == 1
     assert call(h=None) == 1 and call(x=None) == 1 and call(c=None) == 1
