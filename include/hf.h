@@ -245,8 +245,9 @@ hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, u
 
 /*
  * Checker: decodes every chunk of d_out from its offset with the canonical
- * First/Entry/rev tables (treeless decoding, Sec. 4.2.2) and compares it
- * with d_sym_expected.  d_result (uint64[2]) receives {number of
+ * First/Entry/rev tables (treeless decoding, Sec. 4.2.2), one bit at a time
+ * and one lane per chunk, independently of hf_decode's tables, and compares
+ * it with d_sym_expected.  It needs no workspace.  d_result (uint64[2]) receives {number of
  * mismatching symbols (a chunk whose decoding ends off its next offset
  * counts one more), index of the first mismatching symbol or n if none}.
  * Raises HF_ERR_MISMATCH in *d_status when the count is not zero.
@@ -254,8 +255,7 @@ hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, u
 hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets,
                           uint64_t n, uint32_t sym_bytes, uint32_t chunk_symbols,
                           const hf_codebook* book, const void* d_sym_expected,
-                          uint64_t* d_result, void* d_ws, size_t ws_bytes, uint32_t* d_status,
-                          void* stream);
+                          uint64_t* d_result, uint32_t* d_status, void* stream);
 
 /*
  * Batched encoding of many independent streams, each with its own symbol

@@ -237,15 +237,14 @@ hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, u
   if (n > 0 && (!d_ws || ws_bytes < hf::decode_workspace_bytes() || ((uintptr_t)d_ws & 255)))
     return HF_ERR_WORKSPACE;
   return launch_result(hf::launch_decode(d_in, d_chunk_bit_offsets, n, sym_bytes, log2u(chunk_symbols), *book,
-                                         d_sym_out, d_ws, d_status, (hipStream_t)stream, hf::take_main_timer()));
+                                         d_sym_out, d_ws, d_status, num_cus(), (hipStream_t)stream,
+                                         hf::take_main_timer()));
 }
 
 hf_status hf_decode_check(const uint32_t* d_out, const uint64_t* d_chunk_bit_offsets, uint64_t n,
                           uint32_t sym_bytes, uint32_t chunk_symbols, const hf_codebook* book,
-                          const void* d_sym_expected, uint64_t* d_result, void* d_ws,
-                          size_t ws_bytes, uint32_t* d_status, void* stream) {
-  (void)d_ws;
-  (void)ws_bytes;
+                          const void* d_sym_expected, uint64_t* d_result, uint32_t* d_status,
+                          void* stream) {
   if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
       !d_chunk_bit_offsets || !d_result || !d_status || (n > 0 && (!d_out || !d_sym_expected)))
     return HF_ERR_ARG;

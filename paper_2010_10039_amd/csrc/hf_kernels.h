@@ -142,7 +142,7 @@ size_t decode_workspace_bytes();
 
 hipError_t launch_decode(const uint32_t* words, const uint64_t* offsets, uint64_t n, uint32_t sym_bytes,
                          uint32_t chunk_log2, const hf_codebook& book, void* out, void* ws, uint32_t* status,
-                         hipStream_t stream, const KernelTimer& timer);
+                         int num_cus, hipStream_t stream, const KernelTimer& timer);
 
 hipError_t launch_decode_check(const uint32_t* words, const uint64_t* offsets, uint64_t n,
                                uint32_t sym_bytes, uint32_t chunk_log2, const hf_codebook& book,

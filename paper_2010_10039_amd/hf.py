@@ -73,8 +73,7 @@ _lib.hf_build_codebook.restype = ctypes.c_int
 _lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _U32, _P, _P, _U64,
                            _P, _P, _SZ, _P, _P]
 _lib.hf_encode.restype = ctypes.c_int
-_lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P,
-                                 _SZ, _P, _P]
+_lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P, _P]
 _lib.hf_decode_check.restype = ctypes.c_int
 _lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P, _P]
 _lib.hf_lorenzo_histogram.restype = ctypes.c_int
@@ -285,7 +284,7 @@ def hf_encode(sym: torch.Tensor, book: Codebook, chunk_symbols: int = 4096, redu
 
 
 def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor, chunk_symbols: int,
-                    book: Codebook, result: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    book: Codebook, result: torch.Tensor | None = None,
                     status: torch.Tensor | None = None) -> torch.Tensor:
     """Returns int64[2] = (mismatches, first mismatching index or n)."""
     sb = _sym_bytes(sym)
@@ -295,8 +294,7 @@ def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor,
         status = new_status(sym.device)
     s = book.struct()
     _check(_lib.hf_decode_check(_ptr(out), _ptr(offsets), sym.numel(), sb, chunk_symbols, ctypes.byref(s),
-                                _ptr(sym), _ptr(result), _ptr(ws), 0 if ws is None else ws.numel(),
-                                _ptr(status), _stream()), "hf_decode_check")
+                                _ptr(sym), _ptr(result), _ptr(status), _stream()), "hf_decode_check")
     return result
 
 

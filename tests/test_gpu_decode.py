@@ -4,6 +4,8 @@ The decoder is fed the oracle's own stream, offsets and codebook, so it is
 checked independently of the GPU encoder: every decoded symbol must equal
 the input and the oracle's serial decode.  Then the GPU encoder's output
 round-trips, and streams that are no valid encoding raise HF_ERR_STREAM."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -148,3 +150,46 @@ def test_decode_flags_invalid_stream():
     bad[1] += 1
     _, code = gpu_decode(words, bad, x.size, np.uint16, 4096, book)
     assert code == hf.HF_ERR_STREAM
+
+
+def test_decode_fixed_length_code():
+    """256 equally frequent bytes: every code is 8 bits, so a lane that starts
+    off a code boundary never resynchronises; lane regions are multiples of
+    the gcd of the code lengths, which keeps every start on a boundary."""
+    x = np.tile(np.arange(256, dtype=np.uint8), 4001)
+    np.random.default_rng(5).shuffle(x)
+    ref = check(x, 256, 4096)
+    assert set(np.unique(ref.cl[ref.cl > 0]).tolist()) == {8}
+
+
+def test_decode_even_lengths_only():
+    """Code lengths 2 and 4 only (gcd 2)."""
+    h = np.array([4] * 3 + [1] * 4, np.uint32) * 1000
+    x = np.repeat(np.arange(7, dtype=np.uint16), h)
+    np.random.default_rng(6).shuffle(x)
+    ref = check(x, 16, 4096)
+    assert set(np.unique(ref.cl[ref.cl > 0]).tolist()) == {2, 4}
+
+
+def test_decode_near_fixed_length_code():
+    """Mostly 8-bit codes with a few 7- and 9-bit ones: lanes resynchronise
+    slowly, so the restart rounds run long chains."""
+    rng = np.random.default_rng(7)
+    p = np.ones(256)
+    p[:8] = 2.5
+    p /= p.sum()
+    x = rng.choice(256, size=2_000_003, p=p).astype(np.uint8)
+    ref = check(x, 256, 4096)
+    assert ref.cl[ref.cl > 0].min() < 8 < ref.cl.max()
+
+
+@functools.lru_cache(maxsize=1)
+def _lorenzo_full():
+    return W.make("lorenzo3d_512cube_u16_A1024")
+
+
+@pytest.mark.parametrize("chunk", [1024, 4096, 65536])
+def test_decode_full_lorenzo_stream(chunk):
+    """The whole 134 M-symbol Lorenzo code stream, against the input and the
+    oracle's serial decode."""
+    check(_lorenzo_full(), 1024, chunk)
