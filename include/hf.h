@@ -225,6 +225,28 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
                     uint32_t* d_status, void* stream);
 
 /*
+ * hf_encode without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, output and device errors
+ * are exactly hf_encode's.  The workspace is instead a fixed array of
+ * HF_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, held from the
+ * library's first use on that GPU until the process ends; this call
+ * allocates nothing.  Returns HF_ERR_WORKSPACE if hf_encode's workspace for
+ * this slab count and alphabet would not fit the array (it always fits for
+ * the arguments hf_encode accepts: 16384 slabs take 192 KiB and the table of
+ * a 65536-symbol alphabet 256 KiB), and HF_ERR_LAUNCH if the array's device
+ * address cannot be found.  Nothing needs to start at zero.  All calls
+ * on one GPU share the array: calls that can run at the same time on one
+ * GPU (different streams, or different host threads) race on it and must
+ * not be made; calls ordered on one stream are safe.
+ */
+#define HF_NOALLOC_SCRATCH_BYTES (512u << 10)
+hf_status hf_encode_noalloc(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                            uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t nslabs,
+                            const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,
+                            uint64_t* d_chunk_bit_offsets, uint32_t* d_status, void* stream);
+
+/*
  * Decoder (the inverse path; the paper scopes decoding out, Sec. 1, and
  * gives its tables in Sec. 4.2.2 and Table 1): writes the n symbols encoded
  * in d_in (a stream from hf_encode with its chunk offsets, chunk_symbols as

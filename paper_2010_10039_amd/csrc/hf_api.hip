@@ -71,6 +71,43 @@ uint32_t default_slabs(uint64_t n, uint32_t alphabet, uint32_t sym_bytes) {
   return (uint32_t)(s > 0 ? s : 1);
 }
 
+// Argument rules shared by hf_encode and hf_encode_noalloc; *nslabs = 0 is
+// replaced by the default slab count.
+hf_status check_encode_args(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                            uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t* nslabs,
+                            const uint32_t* d_slab_hist, const uint32_t* d_out, const uint64_t* d_offsets,
+                            const uint32_t* d_status) {
+  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
+      !d_offsets || !d_status || (n > 0 && (!d_sym || !d_out)))
+    return HF_ERR_ARG;
+  if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
+  if (reduce_log2 > (uint32_t)hf::kEncMaxR) return HF_ERR_ARG;
+  if (*nslabs > blocks_of(n) || *nslabs > hf::kMaxSlabs) return HF_ERR_ARG;
+  if (d_slab_hist && (*nslabs == 0 || book->alphabet > hf::kSlabHistMaxAlphabet)) return HF_ERR_ARG;
+  if (n > 0 && *nslabs == 0) *nslabs = default_slabs(n, book->alphabet, sym_bytes);
+  return HF_OK;
+}
+
+// The allocation-free encoder's workspace: a fixed array in device memory,
+// one copy per GPU, alive until the process ends.  Its name is a host-side
+// stand-in; the device address of each GPU's copy is looked up once per
+// device with hipGetSymbolAddress and used everywhere host code needs it.
+__device__ __align__(256) unsigned char scratch[HF_NOALLOC_SCRATCH_BYTES];
+
+void* device_scratch() {
+  static std::mutex mu;
+  static void* addr[64] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
+
 }  // namespace
 
 namespace hf {
@@ -185,20 +222,31 @@ hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_
                     uint64_t* d_chunk_bit_offsets, void* d_ws, size_t ws_bytes,
                     uint32_t* d_status, void* stream) {
   const KernelTimer timer = take_timer();
-  if (!valid_book(book) || !valid_symbols(sym_bytes, book->alphabet, n) || !valid_chunk(chunk_symbols) ||
-      !d_chunk_bit_offsets || !d_status || (n > 0 && (!d_sym || !d_out)))
-    return HF_ERR_ARG;
-  if (((uintptr_t)d_sym % sym_bytes) != 0) return HF_ERR_ARG;
-  if (reduce_log2 > (uint32_t)hf::kEncMaxR) return HF_ERR_ARG;
-  if (nslabs > blocks_of(n) || nslabs > hf::kMaxSlabs) return HF_ERR_ARG;
-  if (d_slab_hist && (nslabs == 0 || book->alphabet > hf::kSlabHistMaxAlphabet)) return HF_ERR_ARG;
-  if (n > 0 && nslabs == 0) nslabs = default_slabs(n, book->alphabet, sym_bytes);
-  const uint32_t r = effective_r(reduce_log2);
+  const hf_status st = check_encode_args(d_sym, n, sym_bytes, book, chunk_symbols, reduce_log2, &nslabs,
+                                         d_slab_hist, d_out, d_chunk_bit_offsets, d_status);
+  if (st != HF_OK) return st;
   if (n > 0 && (!d_ws || ws_bytes < hf::encode_workspace_bytes(nslabs, book->alphabet) || ((uintptr_t)d_ws & 255)))
     return HF_ERR_WORKSPACE;
-  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), r, nslabs,
-                                         d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,
+  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), effective_r(reduce_log2),
+                                         nslabs, d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,
                                          d_ws, d_status, (hipStream_t)stream, timer));
+}
+
+hf_status hf_encode_noalloc(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
+                            uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t nslabs,
+                            const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,
+                            uint64_t* d_chunk_bit_offsets, uint32_t* d_status, void* stream) {
+  const KernelTimer timer = take_timer();
+  const hf_status st = check_encode_args(d_sym, n, sym_bytes, book, chunk_symbols, reduce_log2, &nslabs,
+                                         d_slab_hist, d_out, d_chunk_bit_offsets, d_status);
+  if (st != HF_OK) return st;
+  if (n > 0 && hf::encode_workspace_bytes(nslabs, book->alphabet) > HF_NOALLOC_SCRATCH_BYTES)
+    return HF_ERR_WORKSPACE;
+  void* ws = nullptr;
+  if (n > 0 && (ws = device_scratch()) == nullptr) return HF_ERR_LAUNCH;
+  return launch_result(hf::launch_encode(d_sym, n, sym_bytes, *book, log2u(chunk_symbols), effective_r(reduce_log2),
+                                         nslabs, d_slab_hist, d_out, out_capacity_words, d_chunk_bit_offsets,
+                                         ws, d_status, (hipStream_t)stream, timer));
 }
 
 size_t hf_paper_workspace_bytes(uint64_t n, uint32_t chunk_log2) {

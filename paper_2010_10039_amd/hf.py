@@ -73,6 +73,9 @@ _lib.hf_build_codebook.restype = ctypes.c_int
 _lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _U32, _P, _P, _U64,
                            _P, _P, _SZ, _P, _P]
 _lib.hf_encode.restype = ctypes.c_int
+_lib.hf_encode_noalloc.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _U32, _P, _P, _U64,
+                                   _P, _P, _P]
+_lib.hf_encode_noalloc.restype = ctypes.c_int
 _lib.hf_decode_check.argtypes = [_P, _P, _U64, _U32, _U32, ctypes.POINTER(hf_codebook), _P, _P, _P, _P]
 _lib.hf_decode_check.restype = ctypes.c_int
 _lib.hf_lorenzo_histogram.argtypes = [_P, _U32, _U32, _U32, ctypes.c_float, _U32, _P, _P, _U32, _P, _P, _P]
@@ -281,6 +284,18 @@ def hf_encode(sym: torch.Tensor, book: Codebook, chunk_symbols: int = 4096, redu
                           _ptr(status), _stream()),
            "hf_encode")
     return out, offsets
+
+
+def hf_encode_noalloc(sym: torch.Tensor, book: Codebook, out: torch.Tensor, offsets: torch.Tensor,
+                      status: torch.Tensor, chunk_symbols: int = 4096, reduce_log2: int = 0, nslabs: int = 0,
+                      slab_hist: torch.Tensor | None = None) -> None:
+    """hf_encode with the library's fixed device scratch in place of a
+    workspace: every buffer is the caller's, nothing is allocated."""
+    s = book.struct()
+    _check(_lib.hf_encode_noalloc(_ptr(sym), sym.numel(), _sym_bytes(sym), ctypes.byref(s), chunk_symbols,
+                                  reduce_log2, nslabs, _ptr(slab_hist), _ptr(out), out.numel(), _ptr(offsets),
+                                  _ptr(status), _stream()),
+           "hf_encode_noalloc")
 
 
 def hf_decode_check(out: torch.Tensor, offsets: torch.Tensor, sym: torch.Tensor, chunk_symbols: int,
