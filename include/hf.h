@@ -114,9 +114,13 @@ uint32_t hf_slab_count(uint64_t n, uint32_t alphabet);
  * overwritten.  If d_slab_hist is not NULL (then nslabs >= 1, alphabet <=
  * 4096), d_slab_hist[g * alphabet + s] (uint32[nslabs * alphabet]) receives
  * the count of s inside slab g.  Symbols >= alphabet are not counted and
- * raise HF_ERR_SYMBOL in *d_status.  Each workgroup keeps interleaved
- * replicated sub-histograms in LDS and merges them into d_hist with one
- * atomic per non-zero bin.
+ * raise HF_ERR_SYMBOL in *d_status.  Each workgroup counts its slab in
+ * interleaved replicated sub-histograms in LDS and stores the slab's row of
+ * counts (into d_slab_hist, or, when that is NULL and the alphabet is at
+ * most 4096, into the workspace); a second kernel then sums the rows into
+ * d_hist.  Alphabets above 4096 keep no rows: each workgroup adds its
+ * totals to d_hist with one global atomic per non-zero bin, in passes over
+ * bin windows that fit LDS.
  */
 hf_status hf_histogram(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint32_t alphabet,
                        uint32_t* d_hist, uint32_t nslabs, uint32_t* d_slab_hist, void* d_ws,

@@ -47,12 +47,14 @@ def beta_class(beta: float) -> int:
 
 
 def paper_rule(beta: float | None) -> int:
-    """r = 4 - floor(log2 beta), limited to the factors the batch path
-    instantiates (Sec. 4.3); without a beta, the middle choice."""
+    """The library's reduction-factor rule (hf_reduction_factor: Sec. 4.3,
+    r = 4 - floor(log2 beta)), limited to the factors the batch path
+    instantiates; without a beta, the middle choice."""
     if beta is None:
         return 4
-    r = 4 - (int(math.floor(math.log2(beta))) if beta >= 1.0 else 0)
-    return max(R_CHOICES[0], min(R_CHOICES[-1], r))
+    from paper_2010_10039_amd import hf
+
+    return max(R_CHOICES[0], min(R_CHOICES[-1], hf.hf_reduction_factor(float(beta))))
 
 
 def bucket_key(sym_bytes: int, alphabet: int, beta: float | None) -> str:
