@@ -3,6 +3,8 @@
 Every stream of a batch must come out exactly as the oracle encodes it
 alone: histogram, book, every output word and every chunk offset, whatever
 the other streams are (sizes, widths, alphabets, reduction factors)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -172,3 +174,26 @@ def test_batch_full_size_sample():
     assert np.all(enc.status.cpu().numpy() == 0)
     for i in range(0, 64, 8):
         check_stream(enc, i, _np(syms[i]), alph[i], 4096)
+
+
+def test_batch_full_512_streams():
+    """The whole batched workload: 512 streams of 2^16 to 2^26 symbols with
+    the autotuner's chunk size and reduction factor per stream, every 4th
+    stream compared with the oracle (the others decode back to their input)."""
+    from paper_2010_10039_amd import autotune
+
+    syms, alph = W.batched_streams(512, seed=1000, device="cuda")
+    tuner = autotune.Autotuner.load(os.path.join(os.path.dirname(autotune.__file__), "tuning_mi355x.json"))
+    picks = [tuner.choose(t.element_size(), A, None) for t, A in zip(syms, alph)]
+    enc = hf.BatchEncoder(syms, alph, [c.chunk for c in picks], [c.r for c in picks])
+    for o in enc.outs:
+        o.fill_(SENTINEL)
+    enc.run()
+    torch.cuda.synchronize()
+    assert np.all(enc.status.cpu().numpy() == 0)
+    for i in range(0, 512, 4):
+        check_stream(enc, i, _np(syms[i]), alph[i], picks[i].chunk)
+    for i in range(512):
+        if i % 4 and syms[i].numel():
+            r = hf.hf_decode_check(enc.outs[i], enc.offsets[i], syms[i], picks[i].chunk, enc.books[i])
+            assert r.cpu().tolist() == [0, syms[i].numel()], i

@@ -5,6 +5,8 @@ bins, code lengths, codewords, First/Entry/rev tables, info, every output
 word and every chunk offset.  Inputs are seeded; sizes span many tiles with
 ragged tails; the full-size workloads are compared whole (the oracle
 finishes them in seconds)."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -439,3 +441,26 @@ def test_full_lorenzo_512cube_u16():
 
 def test_full_zipf_100M_u8():
     _full(W.make("zipf_100M_u8_A256"), 256, 4096)
+
+
+@functools.lru_cache(maxsize=1)
+def _zipf_full():
+    return W.make("zipf_100M_u8_A256")
+
+
+@pytest.mark.parametrize("chunk", [1 << 10, 1 << 11, 1 << 13, 1 << 14, 1 << 15, 1 << 16])
+def test_full_zipf_100M_u8_chunk_sweep(chunk):
+    """The 10^8-byte text-like stream at every chunk size of the sweep
+    (2^12 is covered above): the GPU path, with the library's default slabs
+    and reduction factor, against the oracle's words and offsets."""
+    x = _zipf_full()
+    d = _dev(x)
+    enc = hf.Encoder(x.size, 256, chunk)
+    out, offs = enc.run(d)
+    torch.cuda.synchronize()
+    hf.raise_on_status(enc.status, "encode")
+    ref = oracle.codebook(oracle.histogram(x, 256))
+    ref_words, ref_offs, tb = oracle.encode(x, ref, chunk)
+    nw = (tb + 31) // 32
+    assert np.array_equal(_u64(offs), ref_offs)
+    assert np.array_equal(_u32(out[:nw]), ref_words[:nw])

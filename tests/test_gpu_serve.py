@@ -77,3 +77,38 @@ def test_served_latencies_are_recorded():
     assert len(lat) == 12 and all(0 < v < wall for v in lat)
     assert all(r.status == 0 for r in loop.finished)
     assert loop.arena.used == 0
+
+
+def test_served_mix_with_solo_and_512MiB_requests():
+    """Small batched requests mixed with requests of at least 32 MiB (which
+    the loop launches alone) and one of 512 MiB: each result equals the same
+    request encoded alone and the oracle's stream."""
+    small = _requests(12, seed=4000, qps=20_000.0, min_bytes=2.0 ** 16, max_bytes=2.0 ** 22)
+    big = _requests(3, seed=4100, qps=20_000.0, min_bytes=2.0 ** 25, max_bytes=2.0 ** 26)
+    huge = _requests(1, seed=4200, qps=20_000.0, min_bytes=2.0 ** 29, max_bytes=2.0 ** 29)
+    reqs = sorted(small + big + huge, key=lambda r: r.arrival)
+    for i, r in enumerate(reqs):
+        r.rid = i
+    assert sum(r.nbytes >= 32 << 20 for r in reqs) >= 4 and max(r.nbytes for r in reqs) >= (512 << 20) - 2
+    loop = S.serve(reqs, capacity=6 << 30, slots=4, max_batch=8, keep_results=True)
+    torch.cuda.synchronize()
+    assert len(loop.finished) == len(reqs) and not loop.rejected
+    for r in reqs:
+        assert r.status == 0, (r.rid, r.status)
+        res = r.result
+        e = _alone(r)
+        nbits = int(e.offsets[-1].item())
+        nw = (nbits + 31) // 32
+        assert torch.equal(res.hist, e.hist), r.rid
+        assert torch.equal(res.offsets, e.offsets), r.rid
+        assert torch.equal(res.out[:nw], e.out[:nw]), r.rid
+        x = r.sym.cpu().numpy()
+        x = x.view(np.uint16) if x.dtype == np.int16 else x
+        ref = oracle.codebook(oracle.histogram(x, r.alphabet))
+        words, offs, tb = oracle.encode(x, ref, r.chunk)
+        assert tb == nbits, r.rid
+        assert np.array_equal(res.offsets.cpu().numpy().view(np.uint64), offs), r.rid
+        assert np.array_equal(res.out[:nw].cpu().numpy().view(np.uint32), words[:nw]), r.rid
+        del e
+        loop.release(r)
+    assert loop.arena.used == 0
