@@ -255,14 +255,19 @@ hf_status hf_encode_noalloc(const void* d_sym, uint64_t n, uint32_t sym_bytes, c
  * gives its tables in Sec. 4.2.2 and Table 1): writes the n symbols encoded
  * in d_in (a stream from hf_encode with its chunk offsets, chunk_symbols as
  * used there, and the same codebook) to d_sym_out (n * sym_bytes bytes).
- * Chunks are decoded in parallel, each from its offset, by treeless
- * canonical decoding: the first l bits v form a code of length l when
- * First[l] <= v < First[l] + (Entry[l + 1] - Entry[l]); its symbol is
- * rev[Entry[l] + v - First[l]].  Codes of up to 12 bits are resolved with
- * one lookup in a table of all 12-bit prefixes, built in d_ws
+ * Treeless canonical decoding: the first l bits v form a code of length l
+ * when First[l] <= v < First[l] + (Entry[l + 1] - Entry[l]) and l is the
+ * smallest such length; its symbol is rev[Entry[l] + v - First[l]].  Each
+ * chunk, from its offset, is decoded by one wave whose lanes start at fixed
+ * bit strides and resynchronise (a decode begun off a code boundary falls
+ * into step with the true one after a few codes), then decode again from
+ * their true starts into their output positions.  A table of every 12-bit
+ * prefix (its code, or its range of code lengths) is built in d_ws
  * (hf_decode_workspace_bytes(), 16 KiB, 256-byte aligned).  A chunk that
- * meets a bit pattern that is no code, or ends off its next offset, raises
- * HF_ERR_STREAM (its symbols are then unspecified).
+ * meets a bit pattern that is no code, ends off its next offset, or holds
+ * another number of codes than its symbols raises HF_ERR_STREAM (its
+ * symbols are then unspecified).  d_in must hold ceil(offsets[nchunks] / 32)
+ * words.
  */
 size_t hf_decode_workspace_bytes(void);
 hf_status hf_decode(const uint32_t* d_in, const uint64_t* d_chunk_bit_offsets, uint64_t n,

@@ -1,8 +1,8 @@
 // hf_codebook.hip -- stages 2 and 3: parallel Huffman code lengths and
 // canonical codewords (Sec. 4.2, Algorithm 1 of the paper).
 //
-// One workgroup (256 lanes up to 4096 symbols, else 1024) builds the whole
-// book.  The paper runs its
+// One workgroup of 1024 lanes builds the whole book (the batched path
+// launches one 256-lane workgroup per stream).  The paper runs its
 // construction as cooperative grid-wide kernels over global memory; a
 // codebook of a few thousand used symbols fits one gfx950 workgroup's LDS
 // (160 KiB), where a barrier costs ~100 cycles instead of a grid sync, so the
@@ -14,7 +14,7 @@
 //     unused symbols receive cl = cw = 0 at once;
 //  2. sort leaves by (count, u) -- u preserves symbol order -- on 48-bit keys
 //     (count << 16 | u): rank sort up to 512 used symbols, a stable LSD radix
-//     sort on the count above (4 bits a pass); the paper sorts with Thrust;
+//     sort on the count above (8 bits a pass); the paper sorts with Thrust;
 //  3. GenerateCL: rounds of the parallel two-queue construction.  t = sum of
 //     the two lightest available nodes (leaf before internal on equal
 //     weight); every unconsumed leaf with weight <= t and every queued

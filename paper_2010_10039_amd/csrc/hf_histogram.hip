@@ -36,60 +36,68 @@ __device__ __forceinline__ uint32_t sym_load(const void* p, uint64_t i) {
   return ((const uint16_t*)p)[i];
 }
 
-// Count one symbol into the LDS window.
-__device__ __forceinline__ void hist_count(uint32_t* sub, uint32_t s, uint32_t lo, uint32_t W,
-                                           uint32_t A, uint32_t R, uint32_t rep, bool& bad) {
+// LDS words between replicas: the window (plus the trash bin when it holds
+// the whole alphabet) rounded up to 1 mod 32, so bin b of replica r sits on
+// bank (b + r) mod 32 and lanes of different replicas that hit a popular bin
+// use different banks.
+__host__ __device__ inline uint32_t hist_stride(uint32_t W, uint32_t A) {
+  const uint32_t w = W == A ? W + 1 : W;
+  return (w + 30) / 32 * 32 + 1;
+}
+
+// Count one symbol into the lane's replica of the LDS window.
+__device__ __forceinline__ void hist_count(uint32_t* subr, uint32_t s, uint32_t lo, uint32_t W, uint32_t A,
+                                           bool& bad) {
   uint32_t b = s - lo;  // wraps for s < lo
-  if (b < W) atomicAdd(&sub[b * R + rep], 1u);
+  if (b < W) atomicAdd(&subr[b], 1u);
   bad |= (s >= A);
 }
 
 template <int SB>
-__device__ __forceinline__ void hist_count_vec(uint32_t* sub, uint4 v, uint32_t lo, uint32_t W,
-                                               uint32_t A, uint32_t R, uint32_t rep, bool& bad) {
+__device__ __forceinline__ void hist_count_vec(uint32_t* subr, uint4 v, uint32_t lo, uint32_t W, uint32_t A,
+                                               bool& bad) {
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (SB == 1) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) hist_count(sub, (w[k] >> (8 * j)) & 0xFFu, lo, W, A, R, rep, bad);
+      for (int j = 0; j < 4; ++j) hist_count(subr, (w[k] >> (8 * j)) & 0xFFu, lo, W, A, bad);
     } else {
-      hist_count(sub, w[k] & 0xFFFFu, lo, W, A, R, rep, bad);
-      hist_count(sub, w[k] >> 16, lo, W, A, R, rep, bad);
+      hist_count(subr, w[k] & 0xFFFFu, lo, W, A, bad);
+      hist_count(subr, w[k] >> 16, lo, W, A, bad);
     }
   }
 }
 
 // Whole alphabet in LDS: a symbol outside it is counted in the trash bin A
-// (no branch); a non-zero trash count flags it at the end.  `subr` is the
-// lane's replica base (sub + rep) and a bin is 4 << shift bytes (R = 1 << shift).
-__device__ __forceinline__ void hist_count_all(uint32_t* subr, uint32_t s, uint32_t A, uint32_t shift) {
-  atomicAdd((uint32_t*)((char*)subr + (min(s, A) << shift)), 1u);
+// (no branch); a non-zero trash count flags it at the end.
+__device__ __forceinline__ void hist_count_all(uint32_t* subr, uint32_t s, uint32_t A) {
+  atomicAdd(&subr[min(s, A)], 1u);
 }
 
 template <int SB>
-__device__ __forceinline__ void hist_count_vec_all(uint32_t* subr, uint4 v, uint32_t A, uint32_t shift) {
+__device__ __forceinline__ void hist_count_vec_all(uint32_t* subr, uint4 v, uint32_t A) {
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (SB == 1) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) hist_count_all(subr, (w[k] >> (8 * j)) & 0xFFu, A, shift);
+      for (int j = 0; j < 4; ++j) hist_count_all(subr, (w[k] >> (8 * j)) & 0xFFu, A);
     } else {
-      hist_count_all(subr, w[k] & 0xFFFFu, A, shift);
-      hist_count_all(subr, w[k] >> 16, A, shift);
+      hist_count_all(subr, w[k] & 0xFFFFu, A);
+      hist_count_all(subr, w[k] >> 16, A);
     }
   }
 }
 
-// Counts symbols [s_lo, s_hi) into the LDS window: scalar head up to the
-// first 16-byte boundary, 16-byte vectors (four in flight per lane), scalar
-// tail.  ALL: the window is the whole alphabet plus a trash bin (lo = 0,
-// W = A); otherwise symbols outside [lo, lo + W) are skipped.
+// Counts symbols [s_lo, s_hi) into the lane's replica `subr` of the LDS
+// window: scalar head up to the first 16-byte boundary, 16-byte vectors
+// (four in flight per lane), scalar tail.  ALL: the window is the whole
+// alphabet plus a trash bin (lo = 0, W = A); otherwise symbols outside
+// [lo, lo + W) are skipped.
 template <int SB, bool ALL>
-__device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict__ sym, uint64_t s_lo,
-                                           uint64_t s_hi, uint32_t lo, uint32_t W, uint32_t A, uint32_t R,
-                                           uint32_t rep, bool& bad) {
+__device__ __forceinline__ void hist_range(uint32_t* subr, const void* __restrict__ sym, uint64_t s_lo,
+                                           uint64_t s_hi, uint32_t lo, uint32_t W, uint32_t A, bool& bad) {
   constexpr uint32_t kPerVec = 16 / SB;
   const uint32_t tid = threadIdx.x;
   const uintptr_t addr = (uintptr_t)sym + s_lo * SB;
@@ -99,35 +107,33 @@ __device__ __forceinline__ void hist_range(uint32_t* sub, const void* __restrict
   const uint4* body = (const uint4*)((const char*)sym + (s_lo + head) * SB);
   uint64_t v = tid;
   constexpr int kUnroll = 4;
-  uint32_t* const subr = sub + rep;
-  const uint32_t shift = (uint32_t)__builtin_ctz(R) + 2;
   for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < nvec; v += kUnroll * (uint64_t)blockDim.x) {
     uint4 q[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (ALL) hist_count_vec_all<SB>(subr, q[u], A, shift);
-      else hist_count_vec<SB>(sub, q[u], lo, W, A, R, rep, bad);
+      if (ALL) hist_count_vec_all<SB>(subr, q[u], A);
+      else hist_count_vec<SB>(subr, q[u], lo, W, A, bad);
     }
   }
   for (; v < nvec; v += blockDim.x) {
-    if (ALL) hist_count_vec_all<SB>(subr, body[v], A, shift);
-    else hist_count_vec<SB>(sub, body[v], lo, W, A, R, rep, bad);
+    if (ALL) hist_count_vec_all<SB>(subr, body[v], A);
+    else hist_count_vec<SB>(subr, body[v], lo, W, A, bad);
   }
   for (uint64_t i = tid; i < head; i += blockDim.x) {
-    if (ALL) hist_count_all(subr, sym_load<SB>(sym, s_lo + i), A, shift);
-    else hist_count(sub, sym_load<SB>(sym, s_lo + i), lo, W, A, R, rep, bad);
+    if (ALL) hist_count_all(subr, sym_load<SB>(sym, s_lo + i), A);
+    else hist_count(subr, sym_load<SB>(sym, s_lo + i), lo, W, A, bad);
   }
   for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x) {
-    if (ALL) hist_count_all(subr, sym_load<SB>(sym, i), A, shift);
-    else hist_count(sub, sym_load<SB>(sym, i), lo, W, A, R, rep, bad);
+    if (ALL) hist_count_all(subr, sym_load<SB>(sym, i), A);
+    else hist_count(subr, sym_load<SB>(sym, i), lo, W, A, bad);
   }
 }
 
-// Words of LDS a window needs: with the whole alphabet, R trash words too.
+// Words of LDS a window needs: R replicas, hist_stride words apart.
 __host__ __device__ inline uint32_t hist_window_words(uint32_t W, uint32_t A, uint32_t R) {
-  return (W == A ? W + 1 : W) * R;
+  return hist_stride(W, A) * R;
 }
 
 // One launch counts bins [lo, lo + W).  Workgroup w takes the contiguous
@@ -150,7 +156,8 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
     for (uint32_t b = tid; b < A; b += blockDim.x) hist[b] = 0;
   __syncthreads();
 
-  const uint32_t rep = tid & (R - 1);
+  const uint32_t Wp = hist_stride(W, A);
+  uint32_t* const subr = sub + (tid & (R - 1)) * Wp;
   bool bad = false;
   const uint64_t g0 = (uint64_t)blockIdx.x * nslabs / gridDim.x;
   const uint64_t g1 = (uint64_t)(blockIdx.x + 1) * nslabs / gridDim.x;
@@ -160,8 +167,8 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
   for (uint64_t g = g0; g < g1; ++g) {
     const uint64_t s_lo = slab_begin(g, nblocks, nslabs, n);
     const uint64_t s_hi = slab_begin(g + 1, nblocks, nslabs, n);
-    if (all) hist_range<SB, true>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
-    else hist_range<SB, false>(sub, sym, s_lo, s_hi, lo, W, A, R, rep, bad);
+    if (all) hist_range<SB, true>(subr, sym, s_lo, s_hi, lo, W, A, bad);
+    else hist_range<SB, false>(subr, sym, s_lo, s_hi, lo, W, A, bad);
     if (slab_hist) {
       __syncthreads();
 #pragma unroll
@@ -169,7 +176,7 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
         const uint32_t b = tid + k * kHistThreads;
         if (b < W) {
           uint32_t c = 0;
-          for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+          for (uint32_t r = 0; r < R; ++r) c += sub[r * Wp + b];
           slab_hist[g * A + lo + b] = c - prev[k];
           prev[k] = c;
         }
@@ -181,13 +188,13 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(
     __syncthreads();
     for (uint32_t b = tid; b < W; b += blockDim.x) {
       uint32_t c = 0;
-      for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+      for (uint32_t r = 0; r < R; ++r) c += sub[r * Wp + b];
       if (c) atomicAdd(&hist[lo + b], c);
     }
   }
   if (all) {
     __syncthreads();
-    if (tid < R && sub[A * R + tid]) bad = true;
+    if (tid < R && sub[tid * Wp + A]) bad = true;
   }
   if (bad) raise_status(status, HF_ERR_SYMBOL);
 }
@@ -229,24 +236,26 @@ __global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const Bat
   const BatchStream& bs = streams[s];
   const uint32_t g = item - bs.item0;
   const uint32_t A = bs.A;
+  const uint32_t Wp = hist_stride(A, A);
   uint32_t R = 1;
-  while (R < 16 && (A + 1) * R * 2 <= lds_words) R *= 2;
+  while (R < 16 && Wp * R * 2 <= lds_words) R *= 2;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < (A + 1) * R; i += blockDim.x) sub[i] = 0;
+  for (uint32_t i = tid; i < Wp * R; i += blockDim.x) sub[i] = 0;
   __syncthreads();
   const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
   const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
   bool bad = false;
-  if (bs.sym_bytes == 1) hist_range<1, true>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
-  else hist_range<2, true>(sub, bs.sym, s_lo, s_hi, 0, A, A, R, tid & (R - 1), bad);
+  uint32_t* const subr = sub + (tid & (R - 1)) * Wp;
+  if (bs.sym_bytes == 1) hist_range<1, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
+  else hist_range<2, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
   __syncthreads();
   uint32_t* row = bs.part + (uint64_t)g * A;
   for (uint32_t b = tid; b < A; b += blockDim.x) {
     uint32_t c = 0;
-    for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
+    for (uint32_t r = 0; r < R; ++r) c += sub[r * Wp + b];
     row[b] = c;
   }
-  if (tid < R && sub[A * R + tid]) bad = true;
+  if (tid < R && sub[tid * Wp + A]) bad = true;
   if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
 }
 
@@ -275,7 +284,9 @@ hipError_t launch_batch_hist_reduce(const BatchStream* d_streams, const uint32_t
 
 // Two replicas of the largest alphabet (more for smaller ones): peaked
 // streams put many lanes on one bin, and every replica splits them.
-uint32_t batch_hist_lds_words(uint32_t max_alphabet) { return std::max<uint32_t>(4096u, 2 * max_alphabet) + 16u; }
+uint32_t batch_hist_lds_words(uint32_t max_alphabet) {
+  return std::max<uint32_t>(4096u, 2 * max_alphabet) + 64u;
+}
 
 hipError_t launch_batch_histogram(const BatchStream* d_streams, const uint32_t* d_item_stream,
                                   const uint32_t* d_items, uint32_t nitems, uint32_t lds_words,
@@ -302,14 +313,17 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStrea
   return hipGetLastError();
 }
 
-// LDS per workgroup: 16 KiB of replicated window (eight 4-wave workgroups
-// per CU); alphabets whose single copy needs more use one copy of up to
-// 32768 bins (128 KiB) and several passes for larger alphabets.
+// LDS per workgroup: up to 32 KiB of replicated window (four 4-wave
+// workgroups per CU, the default slab count's occupancy).  Eight replicas of
+// a 1024-bin alphabet measured 128 -> 82 us on a stream of three popular
+// symbols and the same (LDS atomic issue bound) on the Lorenzo codes.
+// Alphabets whose single copy needs more use one copy of up to 32768 bins
+// (128 KiB) and several passes for larger alphabets.
 static void hist_plan(uint32_t A, uint32_t* W, uint32_t* R) {
-  const uint32_t budget = (16u << 10) + 64u;  // 16 KiB plus the trash bins
-  if ((A + 1) * 4u <= budget) {
+  const uint32_t budget = (32u << 10) + 512u;  // 32 KiB plus the trash bins and stride padding
+  if (hist_stride(A, A) * 4u <= budget) {
     uint32_t r = 1;
-    while (r < 16 && (A + 1) * 4u * (r * 2) <= budget) r *= 2;
+    while (r < 16 && hist_stride(A, A) * 4u * (r * 2) <= budget) r *= 2;
     *W = A;
     *R = r;
   } else {
@@ -349,7 +363,7 @@ hipError_t launch_histogram(const void* sym, uint64_t n, uint32_t sym_bytes, uin
   } else {
     e = launch_fill_u32(hist, A, 0u, stream);
     if (e != hipSuccess) return e;
-    const uint64_t wgs_per_cu = lds <= (16u << 10) + 64u ? 8 : (lds <= (64u << 10) ? 2 : 1);
+    const uint64_t wgs_per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (160u << 10) / lds));
     grid = std::min<uint64_t>((uint64_t)num_cus * wgs_per_cu, (nblocks + 3) / 4);
     if (grid < 1) grid = 1;
     nslabs = (uint32_t)grid;
