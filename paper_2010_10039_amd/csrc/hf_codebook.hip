@@ -9,6 +9,13 @@
 // tree lives in LDS whenever at most kCbLdsMaxUsed symbols are used and in
 // the workspace otherwise (same code, instantiated for both).
 //
+// Books of at most 256 used symbols whose counts sum below 2^32 - 1 (the
+// common case: byte streams, quantization codes) take a one-wave path
+// (build_book_small, below): the histogram is read once into registers,
+// the rounds run with both runs and the queue of internal nodes in one
+// wave's registers, merged by a bitonic network.  Other books take the
+// steps below.
+//
 // Steps:
 //  1. compaction: used symbols in ascending symbol order get compact index u;
 //     unused symbols receive cl = cw = 0 at once;
@@ -374,7 +381,6 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
 
   // ---- 1. compaction -----------------------------------------------------
   compact<NT>(hist, A, t.key, t.usym, book, sh.wtot);
-  const uint32_t P = pow2_ceil(m > 0 ? m : 1);
   for (uint32_t l = tid; l <= kMaxLen; l += NT) sh.cnt[l] = 0;
   if (tid == 0) {
     sh.total = 0;
@@ -710,60 +716,204 @@ struct CbLds {
 
 // ---------------------------------------------------------------------------
 // Books of at most kSmallUsed used symbols whose counts sum below 2^32 - 1:
-// every weight fits 32 bits, the leaves fit four registers of one wave, and
-// one wave runs the rounds with both candidate runs held in registers.
+// every weight fits 32 bits and one wave runs the rounds with both runs and
+// the queue of internal nodes in registers.  A round is that wave's
+// dependent chain of instructions (about 1200 cycles, a third of it the
+// merge network), so every step keeps uniform values scalar and avoids
+// LDS round trips and branches on lane masks.  The rank sort, depths and
+// codewords use every wave or wave 0 as marked.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSmallUsed = 256;
 constexpr uint32_t kInf32 = 0xFFFFFFFFu;
+
+constexpr uint32_t kLeafSlots = kSmallUsed + 2 * 64;  // sorted leaf weights, kInf32 past m
 
 __device__ __forceinline__ uint32_t readlane32(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
+// v of lane (lane ^ D), D a power of two below 64: DPP quad permutes for 1
+// and 2, row shifts left and right on alternate 4-lane banks for 4, a row
+// rotation for 8, and the row-swap instructions for 16 and 32.
+template <int D>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (D == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (D == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (D == 4) {
+    const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0x5, false);    // row_shl:4, banks 0, 2
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x114, 0xF, 0xA, false);  // row_shr:4, banks 1, 3
+  } else if constexpr (D == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (D == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane_id() & 16) ? r[0] : r[1];
+  } else {
+    static_assert(D == 32, "lane distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane_id() & 32) ? r[0] : r[1];
+  }
+}
+
+// One half-cleaner of an ascending bitonic merge of the wave's 64 keys: of
+// lanes l and l ^ D, the one with bit D clear keeps the smaller key.
+template <int D>
+__device__ __forceinline__ uint64_t half_clean(uint64_t k) {
+  const uint32_t lo = lane_xor<D>((uint32_t)k), hi = lane_xor<D>((uint32_t)(k >> 32));
+  const uint64_t p = ((uint64_t)hi << 32) | lo;
+  return ((p < k) != ((lane_id() & D) != 0)) ? p : k;
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t half_clean(uint32_t k) {
+  const uint32_t p = lane_xor<D>(k);
+  return (lane_id() & D) ? max(p, k) : min(p, k);
+}
+
+// A bitonic sequence of 64 keys, one per lane, sorted ascending.
+template <typename K>
+__device__ __forceinline__ K bitonic_merge(K k) {
+  k = half_clean<32>(k);
+  k = half_clean<16>(k);
+  k = half_clean<8>(k);
+  k = half_clean<4>(k);
+  k = half_clean<2>(k);
+  return half_clean<1>(k);
+}
+__device__ __forceinline__ uint64_t bitonic_merge64(uint64_t k) { return bitonic_merge<uint64_t>(k); }
+__device__ __forceinline__ uint32_t bitonic_merge32(uint32_t k) { return bitonic_merge<uint32_t>(k); }
+
+// Merged position p holds node ref r (r < 256: leaf lc + r; else internal
+// node ih + r - 256) and, on even p, the pair sum s: the nodes at positions
+// 2k and 2k + 1 get parent it + k, whose weight is recorded.  Lanes past the
+// pairs write their sinks.
+__device__ __forceinline__ void link_merged(uint32_t r, uint32_t s, uint32_t p, uint32_t pairs, uint32_t lc,
+                                            uint32_t ih, uint32_t it, uint16_t* parl, uint16_t* pari,
+                                            uint32_t* iw, uint16_t* par_sink, uint32_t* iw_sink) {
+  const bool in_pair = p < 2 * pairs;
+  uint16_t* dst = r < 256 ? parl + lc + r : pari + ih + (r - 256);
+  *(in_pair ? dst : par_sink) = (uint16_t)(it + (p >> 1));
+  *(in_pair && !(p & 1) ? iw + it + (p >> 1) : iw_sink) = s;
+}
+
+// A wave-uniform value kept in a scalar register.
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// One round's merge of leaves [lc, lc + a) and internal nodes [ih, ih + b)
+// through LDS, for runs longer than a register: each node's merged position
+// is its index plus a binary search in the other run (leaves first on equal
+// weight); positions 2k and 2k + 1 get parent it + k, whose weight is
+// accumulated in iw[it + k] (zero beforehand).
+__device__ __noinline__ void merge_through_lds(const uint32_t* lw, uint32_t* iw, uint16_t* parl, uint16_t* pari,
+                                               uint32_t lc, uint32_t ih, uint32_t it, uint32_t a, uint32_t b,
+                                               uint32_t pairs) {
+  wave_sync();  // every queued weight is in LDS
+  for (uint32_t j = lane_id(); j < a; j += kWave) {
+    const uint32_t w = lw[lc + j];
+    uint32_t lo = ih, hi = it;  // first internal node not lighter than w
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (iw[md] < w) lo = md + 1;
+      else hi = md;
+    }
+    const uint32_t pos = j + (lo - ih);
+    if (pos < 2 * pairs) {
+      parl[lc + j] = (uint16_t)(it + (pos >> 1));
+      atomicAdd(&iw[it + (pos >> 1)], w);
+    }
+  }
+  for (uint32_t q = lane_id(); q < b; q += kWave) {
+    const uint32_t w = iw[ih + q];
+    uint32_t lo = lc, hi = lc + a;  // first leaf heavier than w
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (lw[md] <= w) lo = md + 1;
+      else hi = md;
+    }
+    const uint32_t pos = q + (lo - lc);
+    if (pos < 2 * pairs) {
+      pari[ih + q] = (uint16_t)(it + (pos >> 1));
+      atomicAdd(&iw[it + (pos >> 1)], w);
+    }
+  }
+  wave_sync();
+}
+
+// 32-bit sort keys of a small book: words 3072 .. 3327 of mw (free until
+// the codewords, which use words 0 .. 194 and 2048 .. 2112).
+__device__ __forceinline__ uint32_t* small_key32(CbLds& L) { return (uint32_t*)L.mw + 3072; }
+
+// Wave-wide running maximum with DPP lane moves, as wave_inclusive_scan:
+// lane 63 ends with the wave's maximum.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));  // row_shr:1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));  // row_shr:2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));  // row_shr:4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));  // row_shr:8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return v;
+}
+
 template <int NT>
-__device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __restrict__ hist, uint32_t m,
-                                                 const hf_codebook& book, uint32_t* status) {
+__device__ __forceinline__ void build_book_small(CbLds& L, uint32_t m, uint32_t narrow, const hf_codebook& book,
+                                                 uint32_t* status) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
-  uint64_t* key = L.key;                    // [m] (count << 16 | u), u = compact index
+  uint64_t* key = L.key;                    // [kSmallUsed] count << 16 | u, u = compact index
+  uint32_t* key32 = small_key32(L);         // [kSmallUsed] count << 8 | u when every count < 2^24
   uint16_t* usym = L.usym;                  // [m] compact index -> symbol
-  uint32_t* lw = (uint32_t*)L.iw;           // [m] leaf weights, sorted by (count, u)
-  uint32_t* iw = lw + kSmallUsed;           // [m-1] internal weights, creation order
+  uint32_t* lw = (uint32_t*)L.iw;           // [kLeafSlots] leaf weights, sorted by (count, u)
+  uint32_t* iw = lw + kLeafSlots;           // [m-1] internal weights, creation order
   uint16_t* lu = L.mid;                     // [m] compact index of each sorted leaf
   uint16_t* parl = L.par;                   // [m] parent of each sorted leaf
   uint16_t* pari = L.par + kSmallUsed;      // [m-1] parent of each internal node
-  uint16_t* dep = L.par + 2 * kSmallUsed;   // [m-1] distance to the current jump target
-  uint16_t* nxt = L.par + 3 * kSmallUsed;   // [m-1] jump target
 
-  // ---- 1. compaction ---------------------------------------------------------
-  compact<NT>(hist, book.alphabet, key, usym, book, L.sh.wtot);
+  // ---- 1. the keys of the used symbols are in LDS (compact_small) -------------
   uint32_t* rk = (uint32_t*)L.mw + 1024;  // [kSmallUsed] rank of each key
-  for (uint32_t i = tid; i < kSmallUsed; i += NT) iw[i] = 0;
   for (uint32_t i = tid; i < kSmallUsed; i += NT) {
+    iw[i] = 0;
     rk[i] = 0;
-    if (i >= m) key[i] = ~0ull;  // above every used key
+    if (i >= m) {  // above every used key
+      key[i] = ~0ull;
+      key32[i] = ~0u;
+    }
   }
+  for (uint32_t i = m + tid; i < kLeafSlots; i += NT) lw[i] = kInf32;
   for (uint32_t l = tid; l <= kMaxLen; l += NT) L.sh.cnt[l] = 0;
   __syncthreads();
 
   // ---- 2. rank sort: rank(e) = #{j : key_j < key_e} ---------------------------
-  // key = count << 16 | u with u the compact (symbol-order) index, so this
-  // is the rank by (count, symbol).  Each of the 16 (block of e, block of j)
-  // pairs of 64-key blocks is counted by one wave from broadcast LDS reads;
-  // the partial ranks meet in LDS.
+  // The key is the count above the compact (symbol-order) index, so this is
+  // the rank by (count, symbol).  Each (block of e, block of j) pair of
+  // 64-key blocks is counted by one wave from broadcast LDS reads, up to the
+  // last used key of the j block (the keys past m are above every used one);
+  // the partial ranks meet in LDS.  Counts below 2^24 take 32-bit keys,
+  // half the LDS traffic.
   {
     const uint32_t nb = (m + kWave - 1) / kWave;
     for (uint32_t p = wave; p < 16; p += NT / kWave) {
       const uint32_t eb = p & 3, jb = p >> 2;
       if (eb >= nb || jb >= nb) continue;
       const uint32_t e = eb * kWave + lane;
-      const uint64_t ke = key[e];
-      const uint64_t* kj = key + jb * kWave;
+      const uint32_t jn = min((uint32_t)kWave, (m - jb * kWave + 15) & ~15u);
       uint32_t c[4] = {0, 0, 0, 0};
-      for (uint32_t j0 = 0; j0 < (uint32_t)kWave; j0 += 16) {
+      if (narrow) {
+        const uint32_t ke = key32[e];
+        const uint32_t* kj = key32 + jb * kWave;
+        for (uint32_t j0 = 0; j0 < jn; j0 += 16) {
 #pragma unroll
-        for (uint32_t j = 0; j < 16; ++j) c[j & 3] += kj[j0 + j] < ke ? 1u : 0u;
+          for (uint32_t j = 0; j < 16; ++j) c[j & 3] += kj[j0 + j] < ke ? 1u : 0u;
+        }
+      } else {
+        const uint64_t ke = key[e];
+        const uint64_t* kj = key + jb * kWave;
+        for (uint32_t j0 = 0; j0 < jn; j0 += 16) {
+#pragma unroll
+          for (uint32_t j = 0; j < 16; ++j) c[j & 3] += kj[j0 + j] < ke ? 1u : 0u;
+        }
       }
       if (e < m) atomicAdd(&rk[e], c[0] + c[1] + c[2] + c[3]);
     }
@@ -771,123 +921,176 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   __syncthreads();
   if (tid < m) {
     const uint32_t r = rk[tid];
-    lw[r] = (uint32_t)(key[tid] >> 16);
+    lw[r] = narrow ? key32[tid] >> 8 : (uint32_t)(key[tid] >> 16);
     lu[r] = (uint16_t)tid;
   }
   __syncthreads();
   if (wave != 0) return;
 
   // ---- 3. GenerateCL rounds, one wave -----------------------------------------
-  // Lane j holds leaf lc + j and internal node ih + j of this round's runs;
-  // the merge position of each comes from counting over the other run.
+  // The merge order is that of keys (weight, tag): tag j for leaf j of the
+  // round's run and 64 + q (or 256 + q) for queued internal node q, so equal
+  // weights put leaves first and keep each run's order, as the merge rule
+  // requires.  Keys are 32-bit (weight << 7 | tag) while the round's heaviest
+  // weight fits 25 bits, else 64-bit (weight << 32 | tag).  While the runs
+  // fit 64 lanes the merge is a bitonic network in registers: runs of at most
+  // 32 share one register (leaves ascending in lanes 0-31, internal nodes
+  // descending in lanes 32-63), longer ones take two (a lane-by-lane compare
+  // of the registers, then a network on each).  Merged position p then sits
+  // in lane p (of the second register from p = 64), so pair k = (2k, 2k+1)
+  // is internal node it + k, its weight the sum of two neighbouring lanes.  A
+  // round with one run only (leaves, or internal nodes) needs no network.
+  // The queue of internal nodes stays in a register between rounds, reversed
+  // (lane 63 - q holds node ih + q), the layout the merges read; the next
+  // queue is gathered from the pair sums by a ds_bpermute.  Longer runs are
+  // merged through LDS by binary searches.  A round is one wave's dependent
+  // chain, so the cursors are kept scalar (readfirstlane) and stores a lane
+  // does not need go to a per-lane sink instead of behind a branch.
   {
+    constexpr uint64_t kPad64 = 0xFFFFFFFF0000FFFFull;  // above every real key
+    constexpr uint32_t kPad32 = 0xFFFFFFFFu;
+    constexpr uint32_t kKey32MaxW = (1u << 25) - 2;      // room for a 7-bit tag below kPad32
+    uint16_t* par_sink = L.par + 4 * kSmallUsed + lane;  // one u16 per lane past the depth words
+    uint32_t* iw_sink = iw + kSmallUsed + lane;          // one word per lane past iw
     uint32_t lc = 0, ih = 0, it = 0;
-    for (uint32_t round = 0; (m - lc) + (it - ih) > 1; ++round) {
+    uint32_t qrev = kInf32;  // lane 63 - q: weight of node ih + q; kInf32 past the queue
+    uint32_t qreg = 1;       // qrev holds the queue (at most 64 nodes)
+    uint32_t RL = lw[lane];  // leaves lc .. lc + 63 (kInf32 past m)
+    for (uint32_t round = 0;; ++round) {
+      const uint32_t b = uniform32(it - ih);
+      if ((m - lc) + b <= 1) break;
       if (round >= m) {  // every round creates at least one node
         if (lane == 0) raise_status(status, HF_ERR_INTERNAL);
         break;
       }
-      const uint32_t b = it - ih;
-      const uint32_t RL = lc + lane < m ? lw[lc + lane] : kInf32;
-      const uint32_t RI = lane < b ? iw[ih + lane] : kInf32;
-      const uint32_t l0 = readlane32(RL, 0), l1 = readlane32(RL, 1);
-      const uint32_t i0 = readlane32(RI, 0), i1 = readlane32(RI, 1);
-      uint32_t w1, w2;  // the two lightest nodes, leaf first on equal weight
-      if (l0 <= i0) {
-        w1 = l0;
-        w2 = l1 <= i0 ? l1 : i0;
-      } else {
-        w1 = i0;
-        w2 = l0 <= i1 ? l0 : i1;
+      uint32_t i0, i1, last_int;
+      if (__builtin_expect(qreg, 1)) {
+        i0 = readlane32(qrev, 63);
+        i1 = readlane32(qrev, 62);
+        last_int = readlane32(qrev, (kWave - b) & 63);  // node ih + b - 1 when b > 0
+      } else {  // more than 64 queued: the queue is in LDS
+        const uint32_t v = iw[ih + (lane & 1)];
+        i0 = readlane32(v, 0);
+        i1 = readlane32(v, 1);
+        last_int = readlane32(iw[it - 1], 0);
       }
+      const uint32_t l0 = readlane32(RL, 0), l1 = readlane32(RL, 1);
+      // the two lightest nodes, leaf first on equal weight
+      const uint32_t w1 = min(l0, i0);
+      const uint32_t w2 = l0 <= i0 ? min(l1, i0) : min(l0, i1);
       const uint32_t tw = w1 + w2;  // <= the sum of all counts < 2^32 - 1
       uint32_t a = (uint32_t)__popcll(__ballot(RL <= tw));
-      if (a == (uint32_t)kWave) {
-        for (uint32_t p = lc + kWave; p < m; p += kWave) {
-          const uint32_t v = p + lane < m ? lw[p + lane] : kInf32;
-          const uint32_t c = (uint32_t)__popcll(__ballot(v <= tw));
+      uint32_t RL2 = kInf32;  // leaves lc + 64 .. lc + 127 when the run reaches them
+      uint32_t last_leaf = readlane32(RL, (a - 1) & 63);
+      if (__builtin_expect(a == (uint32_t)kWave, 0)) {
+        RL2 = lw[lc + kWave + lane];
+        uint32_t c = (uint32_t)__popcll(__ballot(RL2 <= tw));
+        a += c;
+        for (uint32_t p = lc + 2 * kWave; c == (uint32_t)kWave && p < m; p += kWave) {
+          c = (uint32_t)__popcll(__ballot(lw[p + lane] <= tw));
           a += c;
-          if (c < (uint32_t)kWave) break;
         }
+        a = uniform32(a);
+        if (a > (uint32_t)kWave)
+          last_leaf = a <= 2u * kWave ? readlane32(RL2, (a - 1) & 63) : readlane32(lw[lc + a - 1], 0);
       }
       const uint32_t total = a + b, pairs = total >> 1;
-      uint32_t last_leaf, last_int;
-      if (a <= (uint32_t)kWave && b <= (uint32_t)kWave) {
-        // A leaf follows the internal nodes lighter than it, an internal node
-        // the leaves of the run no heavier than it.  Both runs are sorted, so
-        // a loop over the shorter run suffices: one ballot gives how many of
-        // the other run precede each of its elements, and each element of the
-        // other run counts the short-run elements it follows.
-        uint32_t pl = lane, pi = lane;
-        if (b <= a) {
-          const uint64_t amask = a >= (uint32_t)kWave ? ~0ull : (1ull << a) - 1;  // RL past a is not INF
-          for (uint32_t q = 0; q < b; ++q) {
-            const uint32_t wq = readlane32(RI, q);
-            const uint32_t k = (uint32_t)__popcll(__ballot(RL <= wq) & amask);  // leaves [0, k) precede q
-            pl += lane >= k ? 1u : 0u;
-            pi += lane == q ? k : 0u;
+      // the heaviest node of the merge: the run's last leaf unless the last
+      // internal node is heavier; an odd one out waits for the next round
+      const uint32_t leaf_last = uniform32((a != 0) & ((b == 0) | (last_leaf > last_int)));
+      const uint32_t carry_leaf = total & leaf_last & 1u;
+      const uint32_t carry_int = total & (leaf_last ^ 1u) & 1u;
+      const uint32_t maxw = leaf_last ? last_leaf : last_int;
+      const uint32_t lc_next = uniform32(lc + a - carry_leaf);
+      const uint32_t RL_next = lw[lc_next + lane];  // issued before the merge
+      const uint32_t fast = qreg & (a <= (b == 0 ? 2u * kWave : (uint32_t)kWave));
+      if (__builtin_expect(fast, 1)) {
+        const int kk = (int)(63 - lane) - (int)carry_int;  // pair feeding queue slot 63 - lane
+        uint32_t s0, s1 = kInf32;  // pair sums on the lanes named below
+        int src;                   // lane of pair kk's sum
+        if (__builtin_expect(a != 0 && b != 0, 1)) {
+          const uint32_t qi = 63 - lane;
+          uint32_t xw, yw = kInf32, xi, yi = 0;  // merged weights and node refs (256 + q: internal)
+          if (__builtin_expect(maxw <= kKey32MaxW, 1)) {
+            const uint32_t kl = lane < a ? (RL << 7 | lane) : kPad32;
+            const uint32_t ki = qi < b ? (qrev << 7 | (64u + qi)) : kPad32;
+            uint32_t X, Y = kPad32;
+            if (__builtin_expect(a <= 32 && b <= 32, 1)) {
+              X = bitonic_merge32(lane < 32 ? kl : ki);
+            } else {
+              X = bitonic_merge32(min(kl, ki));
+              Y = bitonic_merge32(max(kl, ki));
+            }
+            xw = X >> 7;
+            yw = Y >> 7;
+            xi = (X & 63u) | ((X & 64u) << 2);
+            yi = (Y & 63u) | ((Y & 64u) << 2);
+          } else {
+            const uint64_t kl = lane < a ? ((uint64_t)RL << 32 | lane) : kPad64;
+            const uint64_t ki = qi < b ? ((uint64_t)qrev << 32 | (256u + qi)) : kPad64;
+            uint64_t X, Y = kPad64;
+            if (a <= 32 && b <= 32) {
+              X = bitonic_merge64(lane < 32 ? kl : ki);
+            } else {
+              const bool sw = ki < kl;
+              X = bitonic_merge64(sw ? ki : kl);
+              Y = bitonic_merge64(sw ? kl : ki);
+            }
+            xw = (uint32_t)(X >> 32);
+            yw = (uint32_t)(Y >> 32);
+            xi = (uint32_t)X & 0x1FFu;
+            yi = (uint32_t)Y & 0x1FFu;
           }
+          s0 = xw + lane_xor<1>(xw);
+          s1 = yw + lane_xor<1>(yw);
+          link_merged(xi, s0, lane, pairs, lc, ih, it, parl, pari, iw, par_sink, iw_sink);
+          if (total > (uint32_t)kWave) link_merged(yi, s1, kWave + lane, pairs, lc, ih, it, parl, pari, iw, par_sink, iw_sink);
+          src = (2 * kk) & 63;
+        } else if (b == 0) {
+          // leaves only: merged position p is leaf p of the run
+          s0 = RL + lane_xor<1>(RL);
+          s1 = RL2 + lane_xor<1>(RL2);
+          link_merged(lane, s0, lane, pairs, lc, ih, it, parl, pari, iw, par_sink, iw_sink);
+          if (total > (uint32_t)kWave) link_merged(kWave + lane, s1, kWave + lane, pairs, lc, ih, it, parl, pari, iw, par_sink, iw_sink);
+          src = (2 * kk) & 63;
         } else {
-          for (uint32_t j = 0; j < a; ++j) {
-            const uint32_t wj = readlane32(RL, j);
-            const uint32_t k = (uint32_t)__popcll(__ballot(RI < wj));  // internals [0, k) precede j (RI is INF past b)
-            pi += lane >= k ? 1u : 0u;
-            pl += lane == j ? k : 0u;
-          }
+          // internal nodes only: node ih + q sits in lane 63 - q, pair k = nodes
+          // 2k and 2k + 1, its sum on lane 63 - 2k
+          const uint32_t q = 63 - lane;
+          s0 = qrev + lane_xor<1>(qrev);
+          const bool in_pair = q < 2 * pairs;
+          *(in_pair ? pari + ih + q : par_sink) = (uint16_t)(it + (q >> 1));
+          *(in_pair && !(q & 1) ? iw + it + (q >> 1) : iw_sink) = s0;
+          src = (63 - 2 * kk) & 63;
         }
-        if (lane < a && pl < 2 * pairs) {
-          parl[lc + lane] = (uint16_t)(it + (pl >> 1));
-          atomicAdd(&iw[it + (pl >> 1)], RL);
+        uint32_t nq = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)s0);
+        if (a != 0 && total > (uint32_t)kWave) {
+          const uint32_t f1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)s1);
+          if (kk >= 32) nq = f1;
         }
-        if (lane < b && pi < 2 * pairs) {
-          pari[ih + lane] = (uint16_t)(it + (pi >> 1));
-          atomicAdd(&iw[it + (pi >> 1)], RI);
-        }
-        last_leaf = a ? readlane32(RL, a - 1) : 0u;
-        last_int = b ? readlane32(RI, b - 1) : 0u;
+        if (kk < 0) nq = last_int;  // the carried internal node
+        if (kk >= (int)pairs) nq = kInf32;
+        qrev = nq;
       } else {
-        for (uint32_t j = lane; j < a; j += kWave) {
-          const uint32_t w = lw[lc + j];
-          uint32_t lo = ih, hi = it;  // first internal node not lighter than w
-          while (lo < hi) {
-            const uint32_t md = (lo + hi) >> 1;
-            if (iw[md] < w) lo = md + 1;
-            else hi = md;
-          }
-          const uint32_t pos = j + (lo - ih);
-          if (pos < 2 * pairs) {
-            parl[lc + j] = (uint16_t)(it + (pos >> 1));
-            atomicAdd(&iw[it + (pos >> 1)], w);
-          }
-        }
-        for (uint32_t q = lane; q < b; q += kWave) {
-          const uint32_t w = iw[ih + q];
-          uint32_t lo = lc, hi = lc + a;  // first leaf heavier than w
-          while (lo < hi) {
-            const uint32_t md = (lo + hi) >> 1;
-            if (lw[md] <= w) lo = md + 1;
-            else hi = md;
-          }
-          const uint32_t pos = q + (lo - lc);
-          if (pos < 2 * pairs) {
-            pari[ih + q] = (uint16_t)(it + (pos >> 1));
-            atomicAdd(&iw[it + (pos >> 1)], w);
-          }
-        }
-        last_leaf = a ? readlane32(lw[lc + a - 1], 0) : 0u;
-        last_int = b ? readlane32(iw[it - 1], 0) : 0u;
+        merge_through_lds(lw, iw, parl, pari, lc, ih, it, a, b, pairs);
       }
-      // an odd node out is the heaviest of the merge (internal after leaf on a tie)
-      const bool carry_leaf = (total & 1) && a > 0 && (b == 0 || last_leaf > last_int);
-      const bool carry_int = (total & 1) && !carry_leaf;
-      lc += a - (carry_leaf ? 1u : 0u);
-      ih += b - (carry_int ? 1u : 0u);
-      it += pairs;
-      wave_sync();
+      lc = lc_next;
+      ih = uniform32(ih + b - carry_int);
+      it = uniform32(it + pairs);
+      RL = RL_next;
+      if (__builtin_expect(!fast, 0)) {
+        // after a merge through LDS: reload the queue when it fits a register
+        const uint32_t nb = it - ih;
+        qreg = nb <= (uint32_t)kWave;
+        if (qreg) qrev = 63 - lane < nb ? iw[ih + 63 - lane] : kInf32;
+      }
     }
+    wave_sync();  // parent links complete
   }
 
   // ---- 4. depths of internal nodes by pointer jumping ----------------------------
+  // dn[k] = distance to the current jump target | target << 16, one word a node
+  uint32_t* dn = (uint32_t*)(L.par + 2 * kSmallUsed);
   const uint32_t nint = m - 1, root = m - 2;
   constexpr uint32_t NR = kSmallUsed / kWave;
   uint32_t d[NR], nx[NR];
@@ -902,18 +1105,15 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
 #pragma unroll
     for (uint32_t r = 0; r < NR; ++r) {
       const uint32_t k = r * kWave + lane;
-      if (k < nint) {
-        dep[k] = (uint16_t)d[r];
-        nxt[k] = (uint16_t)nx[r];
-      }
+      if (k < nint) dn[k] = d[r] | nx[r] << 16;
     }
     wave_sync();
     bool active = false;
 #pragma unroll
     for (uint32_t r = 0; r < NR; ++r) {
-      const uint32_t x = nx[r];
-      d[r] += dep[x];
-      nx[r] = nxt[x];
+      const uint32_t v = dn[nx[r]];
+      d[r] += v & 0xFFFFu;
+      nx[r] = v >> 16;
       active |= nx[r] != root;
     }
     wave_sync();
@@ -926,21 +1126,20 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
 #pragma unroll
   for (uint32_t r = 0; r < NR; ++r) {
     const uint32_t k = r * kWave + lane;
-    if (k < nint) dep[k] = (uint16_t)d[r];
+    if (k < nint) dn[k] = d[r];
   }
   wave_sync();
 
   // ---- 5a. leaf lengths, counts per length, total bits ---------------------------
-  uint64_t bits = 0;
-  uint32_t lmax = 0, lmin = 0xFFFFFFFFu;
+  // Total bits in two limbs per lane (this lane's sum of count x length is
+  // below 2^40), each summed exactly by a DPP scan.
+  uint64_t acc = 0;
 #pragma unroll
   for (uint32_t r = 0; r < NR; ++r) {
     const uint32_t e = r * kWave + lane;
     if (e < m) {
-      uint32_t l = (uint32_t)dep[parl[e]] + 1;
-      bits += (uint64_t)lw[e] * l;
-      lmax = max(lmax, l);
-      lmin = min(lmin, l);
+      uint32_t l = (dn[parl[e]] & 0xFFFFu) + 1;
+      acc += (uint64_t)lw[e] * l;
       if (l > kMaxLen) l = kMaxLen;  // flagged below; keeps indexes in range
       const uint32_t u = lu[e];
       L.clu[u] = (uint8_t)l;
@@ -948,33 +1147,30 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
       atomicAdd(&L.sh.cnt[l], 1u);
     }
   }
-  bits = wave_sum_u64(bits);
-  lmax = wave_max_u32(lmax);
-#pragma unroll
-  for (int dd = kWave / 2; dd > 0; dd >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor(lmin, dd, kWave));
+  const uint32_t blo = wave_inclusive_scan((uint32_t)acc & 0xFFFFFFu);  // < 2^30
+  const uint32_t bhi = wave_inclusive_scan((uint32_t)(acc >> 24));      // < 2^22
+  const uint64_t bits = ((uint64_t)readlane32(bhi, 63) << 24) + readlane32(blo, 63);
   wave_sync();
 
   // ---- 5b. First and Entry: lane j holds length j + 1 ---------------------------
-  // first[l] = ceil((first[l+1] + cnt[l+1]) / 2) with first[Lc] = 0 unrolls to
-  // ceil(S / 2^(Lc-l)), S = sum over k > l of cnt[k] 2^(Lc-k) (nested ceilings
-  // of halvings compose); S < 2^53 for n < 2^32.
-  const uint32_t Lc = lmax > kMaxLen ? kMaxLen : lmax;
+  // The lengths present come from one ballot of the counts.  first[l] =
+  // ceil((first[l+1] + cnt[l+1]) / 2) with first[Lc] = 0 unrolls to
+  // ceil((2^Lc - P_l) / 2^(Lc-l)) = 2^l - floor(P_l / 2^(Lc-l)), where P_l =
+  // sum over k <= l of cnt[k] 2^(Lc-k) and P_Lc = 2^Lc (the Kraft sum of a
+  // full tree is 1).  With counts summing below 2^32 no code is longer than
+  // 46 bits, so each term is at most 2^46 and P is summed exactly in two
+  // DPP-scanned limbs.
   const uint32_t len = lane + 1;
   const uint32_t cnt = L.sh.cnt[len];
+  const uint64_t present = __ballot(cnt != 0);
+  const uint32_t lmax = 64 - (uint32_t)__clzll(present), lmin = (uint32_t)__builtin_ctzll(present) + 1;
+  const uint32_t Lc = lmax > kMaxLen ? kMaxLen : lmax;
   const uint32_t below = wave_inclusive_scan(cnt) - cnt;  // codes shorter than len
-  uint64_t fst = 0;
-  {
-    // suffix sum over lanes j > lane of cnt[j + 1] * 2^(Lc - j - 1)
-    const uint64_t term = (len <= Lc) ? ((uint64_t)cnt << (Lc - len)) : 0ull;
-    uint64_t suf = term;
-#pragma unroll
-    for (int dd = 1; dd < kWave; dd <<= 1) {
-      const uint64_t o = __shfl_down(suf, dd, kWave);
-      if ((int)lane + dd < kWave) suf += o;
-    }
-    const uint64_t S = suf - term;
-    if (len < Lc) fst = (S + (1ull << (Lc - len)) - 1) >> (Lc - len);
-  }
+  const uint64_t term = len <= Lc ? (uint64_t)cnt << (Lc - len) : 0ull;
+  const uint32_t plo = wave_inclusive_scan((uint32_t)term & 0xFFFFFFu);  // < 2^30
+  const uint32_t phi = wave_inclusive_scan((uint32_t)(term >> 24));      // < 2^28
+  const uint64_t P = ((uint64_t)phi << 24) + plo;
+  const uint64_t fst = len < Lc ? (1ull << len) - (P >> (Lc - len)) : 0ull;
   book.first[len] = fst;
   book.entry[len] = below;
   uint64_t* fl = (uint64_t*)L.mw;        // [65] first, by length
@@ -1021,41 +1217,124 @@ __device__ __forceinline__ void build_book_small(CbLds& L, const uint32_t* __res
   }
 }
 
-// The whole book from hist[A] by one workgroup of NT lanes.
+// cl = cw = 0 for each of symbols s0 .. s0 + 3 (below A) whose count is 0.
+__device__ __forceinline__ void zero_unused(const uint32_t (&h)[4], uint32_t s0, uint32_t A, const hf_codebook& book) {
+#pragma unroll
+  for (uint32_t v = 0; v < 4; ++v) {
+    if (h[v] == 0 && s0 + v < A) {
+      book.cl[s0 + v] = 0;
+      book.cw[s0 + v] = 0;
+    }
+  }
+}
+
+// The whole book from hist[A] by one workgroup of NT lanes.  Up to 4 NT
+// symbols the histogram is read once: thread t holds the counts of symbols
+// 4t .. 4t+3, wave scans (DPP) give each used symbol its compact index, the
+// number of used symbols, the sum of the counts (two limbs of 24 and 10
+// bits, exact) and the largest count, and a small book is compacted straight
+// from those registers.
 template <int NT>
 __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist, const hf_codebook& book,
                                                char* ws, uint32_t* status, CbLds& L) {
+  constexpr int NW = NT / kWave;
   const uint32_t A = book.alphabet;
   const uint32_t tid = threadIdx.x;
-  uint32_t c = 0, hmax = 0;
-  uint64_t wsum = 0;
-#pragma unroll 8
-  for (uint32_t s = tid; s < A; s += NT) {
-    const uint32_t h = hist[s];
-    c += (h != 0);
-    wsum += h;
-    hmax = max(hmax, h);
-  }
-  wsum = wave_sum_u64(wsum);
-  hmax = wave_max_u32(hmax);
-  if ((tid & (kWave - 1)) == 0) {
-    L.sh.wsum[tid / kWave] = wsum;
-    L.sh.wmax[tid / kWave] = hmax;
-  }
-  uint32_t m;
-  (void)block_exclusive_scan<NT / kWave>(c, L.sh.wtot, &m);  // (its barrier covers wsum and wmax)
+  const uint32_t lane = tid & (kWave - 1), wave = tid / kWave;
+  uint32_t m = 0, wmax = 0;
   uint64_t total = 0;
-  uint32_t wmax = 0;
+  if (A <= 4u * NT) {
+    uint32_t h[4], c = 0, hm = 0;
+    uint64_t sum = 0;
 #pragma unroll
-  for (int w = 0; w < NT / kWave; ++w) {
-    total += L.sh.wsum[w];
-    wmax = max(wmax, L.sh.wmax[w]);
+    for (uint32_t v = 0; v < 4; ++v) {
+      const uint32_t s = 4 * tid + v;
+      h[v] = s < A ? hist[s] : 0u;
+      c += h[v] != 0;
+      sum += h[v];
+      hm = max(hm, h[v]);
+    }
+    const uint32_t cin = wave_inclusive_scan(c);
+    const uint32_t slo = wave_inclusive_scan((uint32_t)sum & 0xFFFFFFu);  // < 2^30 over a wave
+    const uint32_t shi = wave_inclusive_scan((uint32_t)(sum >> 24));      // < 2^16 over a wave
+    const uint32_t mx = wave_inclusive_max(hm);
+    if (lane == kWave - 1) {
+      L.sh.wtot[wave] = cin;
+      L.sh.wsum[wave] = ((uint64_t)shi << 24) + slo;
+      L.sh.wmax[wave] = mx;
+    }
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t t = L.sh.wtot[w];
+      pre += w < (int)wave ? t : 0u;
+      m += t;
+      total += L.sh.wsum[w];
+      wmax = max(wmax, L.sh.wmax[w]);
+    }
+    if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
+      // compaction in symbol order; unused symbols get cl = cw = 0
+      const uint32_t narrow = wmax < (1u << 24);
+      uint32_t* key32 = small_key32(L);
+      uint32_t u = pre + cin - c;
+#pragma unroll
+      for (uint32_t v = 0; v < 4; ++v) {
+        if (h[v]) {
+          if (narrow) key32[u] = h[v] << 8 | u;
+          else L.key[u] = ((uint64_t)h[v] << 16) | u;
+          L.usym[u] = (uint16_t)(4 * tid + v);
+          ++u;
+        }
+      }
+      build_book_small<NT>(L, m, narrow, book, status);
+      // Unused symbols get cl = cw = 0 from the waves that sit out the
+      // rounds (wave 1 also covers wave 0's symbols); the used ones are
+      // written by wave 0, so the two never meet.
+      if (wave != 0) {
+        zero_unused(h, 4 * tid, A, book);
+        if (wave == 1) {
+          const uint32_t s0 = 4 * lane;
+          uint32_t h0[4];
+#pragma unroll
+          for (uint32_t v = 0; v < 4; ++v) h0[v] = s0 + v < A ? hist[s0 + v] : 0u;
+          zero_unused(h0, s0, A, book);
+        }
+      }
+      return;
+    }
+    __syncthreads();  // wtot is reused by the compaction
+  } else {
+    uint32_t c = 0, hm = 0;
+    uint64_t wsum = 0;
+#pragma unroll 8
+    for (uint32_t s = tid; s < A; s += NT) {
+      const uint32_t h = hist[s];
+      c += (h != 0);
+      wsum += h;
+      hm = max(hm, h);
+    }
+    wsum = wave_sum_u64(wsum);
+    hm = wave_max_u32(hm);
+    if (lane == 0) {
+      L.sh.wsum[wave] = wsum;
+      L.sh.wmax[wave] = hm;
+    }
+    (void)block_exclusive_scan<NW>(c, L.sh.wtot, &m);  // (its barrier covers wsum and wmax)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      total += L.sh.wsum[w];
+      wmax = max(wmax, L.sh.wmax[w]);
+    }
+    __syncthreads();  // wtot is reused by the compaction
+    if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
+      compact<NT>(hist, A, L.key, L.usym, book, L.sh.wtot);  // 64-bit keys
+      build_book_small<NT>(L, m, 0, book, status);
+      return;
+    }
   }
-  __syncthreads();  // wtot is reused by the compaction
 
-  if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
-    build_book_small<NT>(L, hist, m, book, status);
-  } else if (m <= kCbLdsMaxUsed) {
+  if (m <= kCbLdsMaxUsed) {
     Tree<uint16_t> t;
     t.key = L.key;
     t.iw = L.iw;

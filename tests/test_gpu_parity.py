@@ -261,6 +261,49 @@ def test_codebook_parity(name):
     assert_book_equal(book, ref)
 
 
+def _random_small_books(count, seed):
+    """Seeded books of 2..256 used symbols, scattered over alphabets up to
+    1024 (one in five up to 65536), with counts that are tiny and tied, uniform, exponential, geometric,
+    all equal, drawn from a few values, or large enough that merged weights
+    pass 2^25 (the 64-bit merge keys): every round shape of the one-wave
+    construction (one run only, runs of at most 32 each, of at most 64 each,
+    and longer runs merged through LDS, then a queue that fits a register
+    again)."""
+    rng = np.random.default_rng(seed)
+    books = []
+    while len(books) < count:
+        kind = len(books) % 7
+        mm = int(rng.integers(2, 257))
+        A = int(rng.integers(mm, 1025)) if len(books) % 5 else int(rng.integers(4097, 65537))
+        h = np.zeros(A, np.int64)
+        pos = rng.choice(A, size=mm, replace=False)
+        if kind == 0:
+            v = rng.integers(1, 5, mm)
+        elif kind == 1:
+            v = rng.integers(1, 1 << 24, mm)
+        elif kind == 2:
+            v = np.maximum(1, np.round(rng.exponential(50, mm))).astype(np.int64)
+        elif kind == 3:
+            v = np.maximum(1, (1e7 * 0.93 ** np.arange(mm))).astype(np.int64)
+        elif kind == 4:
+            v = np.full(mm, 7)
+        elif kind == 5:
+            v = rng.choice([1, 2, 2, 5, 5, 5, 9], size=mm)
+        else:
+            v = rng.integers(1, 0xFFFFFFF0 // (mm + 1), mm)
+        h[pos] = v
+        books.append(h.astype(np.uint32))
+    return books
+
+
+def test_codebook_parity_random_small_books():
+    for i, h in enumerate(_random_small_books(280, seed=77)):
+        ref = oracle.codebook(h)
+        book, code = gpu_book(h)
+        assert code == 0, i
+        assert_book_equal(book, ref)
+
+
 # ---------------------------------------------------------------------------
 # encoding
 # ---------------------------------------------------------------------------
