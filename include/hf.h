@@ -314,8 +314,8 @@ typedef struct hf_stream_desc {
   uint64_t* chunk_bit_offsets;
 } hf_stream_desc;
 
-/* Workspace bytes hf_encode_batch needs for these descriptors (0 if one is
- * invalid). */
+/* Workspace bytes hf_encode_batch and hf_encode_batch_persistent need for
+ * these descriptors (0 if one is invalid). */
 size_t hf_batch_workspace_bytes(const hf_stream_desc* descs, uint32_t nstreams);
 
 /*
@@ -336,6 +336,24 @@ size_t hf_batch_workspace_bytes(const hf_stream_desc* descs, uint32_t nstreams);
  */
 hf_status hf_encode_batch(const hf_stream_desc* descs, uint32_t nstreams, void* d_ws, size_t ws_bytes,
                           uint32_t* d_status, void* stream);
+
+/*
+ * The same work as hf_encode_batch, with the same arguments, workspace
+ * (hf_batch_workspace_bytes) and results, in ONE persistent launch: a grid
+ * of resident workgroups takes work items from a device queue in the order
+ * slab histograms, per-stream histogram sums, codebooks, slab bit totals,
+ * slab encodings, and each item waits only for per-stream device counters
+ * of earlier items (no grid-wide barrier), so the streams' stages overlap.
+ * Every item of the queue depends only on earlier items, so the queue
+ * always drains; a wait that exceeds its spin limit (a fraction of a
+ * second) records HF_ERR_INTERNAL in its stream's status word and closes
+ * the queue instead of hanging.  Calls that share a workspace must not
+ * overlap.
+ * CURRENTLY SWITCHED OFF: returns HF_ERR_LAUNCH and launches nothing (the
+ * kernel's first run made a memory fault whose cause is not found yet).
+ */
+hf_status hf_encode_batch_persistent(const hf_stream_desc* descs, uint32_t nstreams, void* d_ws, size_t ws_bytes,
+                                     uint32_t* d_status, void* stream);
 
 /*
  * Profiling hook: for the next call of hf_histogram, hf_build_codebook,

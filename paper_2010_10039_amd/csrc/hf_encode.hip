@@ -30,7 +30,9 @@
 #include <algorithm>
 #include <mutex>
 
+#include "hf_codebook_dev.h"
 #include "hf_device.h"
+#include "hf_hist_dev.h"
 #include "hf_kernels.h"
 
 namespace hf {
@@ -532,14 +534,10 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(EncArgs a) {
   else encode_slab<R, SB, kModeWide>(a, tab, buf, dummy, sh, g, G, a.bits[g]);
 }
 
-// Batched stage 4: bit total and last 32 content bits of slab g of stream s
-// for work item i = streams[s].item0 + g, from the slab's counts.
-__global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const BatchStream* __restrict__ streams,
-                                                                      const uint32_t* __restrict__ item_stream) {
-  __shared__ uint64_t part[kPreWaves];
-  const uint32_t item = blockIdx.x;
-  const BatchStream& bs = streams[item_stream[item]];
-  const uint32_t g = item - bs.item0;
+// Batched stage 4 for work item (stream bs, slab g): the slab's bit total
+// and last 32 content bits, from its counts (kPreThreads lanes; part: LDS
+// words, one per wave).
+__device__ __forceinline__ void batch_slab_bits_item(const BatchStream& bs, uint32_t g, uint64_t* part) {
   const uint32_t tid = threadIdx.x;
   const uint32_t A = bs.A;
   const uint32_t* row = bs.part + (uint64_t)g * A;
@@ -563,21 +561,19 @@ __global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const Batc
   }
 }
 
-// Batched stage 5: workgroup i encodes slab g of stream s for work item
-// items[i] = streams[s].item0 + g; its first bit is the sum of the bit
-// totals of the stream's earlier slabs.  Each stream has its own alphabet,
-// symbol width and codebook.
+// LDS bytes the batched encoder needs for reduction factor r and alphabets
+// up to A: [tile buffer: T + 8 words][tables][kEncThreads dummy words].
+__host__ __device__ inline size_t batch_encode_lds_bytes(uint32_t r, uint32_t A) {
+  return 4 * (((size_t)kEncThreads << r) + 8 + (size_t)table_words(A) + kEncThreads);
+}
+
+// Batched stage 5 for work item (stream bs, slab g): encodes the slab; its
+// first bit is the sum of the bit totals of the stream's earlier slabs.
+// Each stream has its own alphabet, symbol width and codebook.
 template <int R>
-__global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchStream* __restrict__ streams,
-                                                                   const uint32_t* __restrict__ item_stream,
-                                                                   const uint32_t* __restrict__ items) {
+__device__ __forceinline__ void batch_encode_item(const BatchStream& bs, uint32_t g, uint32_t* lds, EncShared& sh) {
   constexpr uint32_t T = kEncThreads << R;
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ EncShared sh;
   const uint32_t tid = threadIdx.x;
-  const uint32_t item = items[blockIdx.x];
-  const BatchStream& bs = streams[item_stream[item]];
-  const uint32_t g = item - bs.item0;
   EncArgs a;
   a.sym = bs.sym;
   a.n = bs.n;
@@ -630,7 +626,25 @@ __global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchSt
   }
 }
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Batched stage 4: workgroup i handles work item i.
+__global__ __launch_bounds__(kPreThreads) void batch_slab_bits_kernel(const BatchStream* __restrict__ streams,
+                                                                      const uint32_t* __restrict__ item_stream) {
+  __shared__ uint64_t part[kPreWaves];
+  const BatchStream& bs = streams[item_stream[blockIdx.x]];
+  batch_slab_bits_item(bs, blockIdx.x - bs.item0, part);
+}
+
+// Batched stage 5: workgroup i encodes the slab of work item items[i].
+template <int R>
+__global__ __launch_bounds__(kEncThreads) void batch_encode_kernel(const BatchStream* __restrict__ streams,
+                                                                   const uint32_t* __restrict__ item_stream,
+                                                                   const uint32_t* __restrict__ items) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ EncShared sh;
+  const uint32_t item = items[blockIdx.x];
+  const BatchStream& bs = streams[item_stream[item]];
+  batch_encode_item<R>(bs, item - bs.item0, lds, sh);
+}
 
 using EncodeFn = void (*)(EncArgs);
 
@@ -767,6 +781,138 @@ hipError_t launch_encode(const void* sym, uint64_t n, uint32_t sym_bytes, const 
   e = hipGetLastError();
   timer.after(stream);
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch: every stage of every stream in one kernel.
+// ---------------------------------------------------------------------------
+namespace {
+
+using FusedCbLds = CbLdsT<kFusedTreeCap>;
+constexpr uint32_t kFusedSpinLimit = 1u << 18;  // polls (0.1 - 0.3 s); real waits are below a millisecond
+constexpr uint32_t kFusedQueueClosed = 0x7FFFFFFFu;
+
+// Waits until *counter reaches target: lane 0 polls with acquire loads, then
+// every lane acquires.  A counter only counts items that come earlier in the
+// queue, and the earliest unfinished item always has its inputs and a
+// running workgroup, so the wait ends.  The spin limit turns a broken
+// invariant into an error instead of a hang: the stream's status records
+// HF_ERR_INTERNAL and the queue is closed (its head moved past every
+// item), so the grid drains after the items already taken.
+__device__ __forceinline__ void fused_wait(const uint32_t* counter, uint32_t target, uint32_t* status,
+                                           uint32_t* head) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kFusedSpinLimit) {
+        raise_status(status, HF_ERR_INTERNAL);
+        atomicMax(head, kFusedQueueClosed);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publishes a finished item: every lane's stores reach device scope, then
+// one count.
+__device__ __forceinline__ void fused_done(uint32_t* counter) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+// The queue holds, in this order: the slab histograms (hist_items order),
+// the bin-chunk sums (red_items), one codebook per stream, the slab bit
+// totals (item order) and the slab encodings (enc_items order).  Stream s
+// has four counters after sync[0] (the queue head): slabs counted, bin
+// chunks summed, book built, slab totals known.  A reduce item waits for
+// all its stream's slabs, a codebook for all its chunks, a slab total for
+// the book, an encoding for all the stream's slab totals.
+__global__ __launch_bounds__(kEncThreads) void batch_persistent_kernel(FusedArgs f) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ EncShared sh;
+  __shared__ uint64_t part[kPreWaves];
+  __shared__ uint32_t s_item;
+  const uint32_t nh = f.nitems;
+  const uint32_t c_red = nh, c_cb = c_red + f.nred, c_bits = c_cb + f.nstreams, c_enc = c_bits + nh;
+  const uint32_t total = c_enc + nh;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(f.sync, 1u);
+    __syncthreads();
+    const uint32_t i = s_item;
+    __syncthreads();
+    if (i >= total) break;
+    uint32_t* done = nullptr;
+    if (i < c_red) {
+      const uint32_t item = f.hist_items[i];
+      const uint32_t s = f.item_stream[item];
+      const BatchStream& bs = f.streams[s];
+      batch_hist_item(bs, item - bs.item0, lds, f.lds_words);
+      done = f.sync + 1 + 4 * s;
+    } else if (i < c_cb) {
+      const uint32_t r = f.red_items[i - c_red];
+      const BatchStream& bs = f.streams[r >> 6];
+      uint32_t* cnt = f.sync + 1 + 4 * (r >> 6);
+      fused_wait(cnt, bs.nslabs, bs.status, f.sync);
+      batch_reduce_item(bs, r & 63);
+      done = cnt + 1;
+    } else if (i < c_bits) {
+      const uint32_t s = i - c_cb;
+      const BatchStream& bs = f.streams[s];
+      uint32_t* cnt = f.sync + 1 + 4 * s;
+      fused_wait(cnt + 1, bs.n ? (bs.A + kBatchReduceBins - 1) / kBatchReduceBins : 0u, bs.status, f.sync);
+      batch_codebook_item<kEncThreads>(bs, *reinterpret_cast<FusedCbLds*>(lds));
+      done = cnt + 2;
+    } else if (i < c_enc) {
+      const uint32_t item = i - c_bits;
+      const uint32_t s = f.item_stream[item];
+      const BatchStream& bs = f.streams[s];
+      uint32_t* cnt = f.sync + 1 + 4 * s;
+      fused_wait(cnt + 2, 1u, bs.status, f.sync);
+      batch_slab_bits_item(bs, item - bs.item0, part);
+      done = cnt + 3;
+    } else {
+      const uint32_t item = f.enc_items[i - c_enc];
+      const uint32_t s = f.item_stream[item];
+      const BatchStream& bs = f.streams[s];
+      fused_wait(f.sync + 1 + 4 * s + 3, bs.nslabs, bs.status, f.sync);
+      const uint32_t g = item - bs.item0;
+      if (bs.r == 3) batch_encode_item<3>(bs, g, lds, sh);
+      else if (bs.r == 5) batch_encode_item<5>(bs, g, lds, sh);
+      else batch_encode_item<4>(bs, g, lds, sh);
+    }
+    if (done) fused_done(done);
+    else __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+size_t batch_persistent_lds_bytes(const BatchStream* streams, uint32_t nstreams) {
+  size_t b = sizeof(FusedCbLds);
+  for (uint32_t s = 0; s < nstreams; ++s) {
+    b = std::max(b, batch_encode_lds_bytes(streams[s].r, streams[s].A));
+    b = std::max(b, (size_t)4 * hist_stride(streams[s].A, streams[s].A));
+  }
+  return (b + 15) & ~(size_t)15;
+}
+
+hipError_t launch_batch_persistent(const FusedArgs& f, size_t lds_bytes, int num_cus, hipStream_t stream) {
+  const void* fn = (const void*)batch_persistent_kernel;
+  if (lds_bytes > (64u << 10)) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEncThreads, lds_bytes) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint64_t total = 3ull * f.nitems + f.nred + f.nstreams;
+  const uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)std::max(num_cus, 1), std::max<uint64_t>(total, 1));
+  batch_persistent_kernel<<<(uint32_t)grid, kEncThreads, lds_bytes, stream>>>(f);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_slab_bits(const BatchStream* d_streams, const uint32_t* d_item_stream, uint32_t nitems,

@@ -5,9 +5,9 @@
 // the block results are merged into one global histogram.  On gfx950:
 //  - each workgroup reads one contiguous slab of the input with 16-byte
 //    vector loads (several in flight per lane), so HBM sees long streams;
-//  - R replicas of the bin window live in LDS interleaved per bin
-//    (bin b, replica r at word b*R + r), lane l updating replica l % R, so
-//    lanes hitting the same bin land on R different banks;
+//  - R replicas of the bin window live in LDS one after another, a stride
+//    of 1 mod 32 words apart, lane l updating replica l % R, so lanes of
+//    different replicas hitting the same bin land on different banks;
 //  - at the end every non-zero bin is added to the global histogram with
 //    one global atomic, so peaked data costs a few hundred atomics per
 //    workgroup, not one per bin;
@@ -15,8 +15,7 @@
 //    several passes over the input.
 #include <algorithm>
 
-#include "hf_device.h"
-#include "hf_kernels.h"
+#include "hf_hist_dev.h"
 
 namespace hf {
 
@@ -28,112 +27,6 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t count, uint32
 __global__ void fill_u64_kernel(uint64_t* __restrict__ p, uint64_t count, uint64_t value) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < count; i += (uint64_t)gridDim.x * blockDim.x) p[i] = value;
-}
-
-template <int SB>
-__device__ __forceinline__ uint32_t sym_load(const void* p, uint64_t i) {
-  if (SB == 1) return ((const uint8_t*)p)[i];
-  return ((const uint16_t*)p)[i];
-}
-
-// LDS words between replicas: the window (plus the trash bin when it holds
-// the whole alphabet) rounded up to 1 mod 32, so bin b of replica r sits on
-// bank (b + r) mod 32 and lanes of different replicas that hit a popular bin
-// use different banks.
-__host__ __device__ inline uint32_t hist_stride(uint32_t W, uint32_t A) {
-  const uint32_t w = W == A ? W + 1 : W;
-  return (w + 30) / 32 * 32 + 1;
-}
-
-// Count one symbol into the lane's replica of the LDS window.
-__device__ __forceinline__ void hist_count(uint32_t* subr, uint32_t s, uint32_t lo, uint32_t W, uint32_t A,
-                                           bool& bad) {
-  uint32_t b = s - lo;  // wraps for s < lo
-  if (b < W) atomicAdd(&subr[b], 1u);
-  bad |= (s >= A);
-}
-
-template <int SB>
-__device__ __forceinline__ void hist_count_vec(uint32_t* subr, uint4 v, uint32_t lo, uint32_t W, uint32_t A,
-                                               bool& bad) {
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (SB == 1) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) hist_count(subr, (w[k] >> (8 * j)) & 0xFFu, lo, W, A, bad);
-    } else {
-      hist_count(subr, w[k] & 0xFFFFu, lo, W, A, bad);
-      hist_count(subr, w[k] >> 16, lo, W, A, bad);
-    }
-  }
-}
-
-// Whole alphabet in LDS: a symbol outside it is counted in the trash bin A
-// (no branch); a non-zero trash count flags it at the end.
-__device__ __forceinline__ void hist_count_all(uint32_t* subr, uint32_t s, uint32_t A) {
-  atomicAdd(&subr[min(s, A)], 1u);
-}
-
-template <int SB>
-__device__ __forceinline__ void hist_count_vec_all(uint32_t* subr, uint4 v, uint32_t A) {
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (SB == 1) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) hist_count_all(subr, (w[k] >> (8 * j)) & 0xFFu, A);
-    } else {
-      hist_count_all(subr, w[k] & 0xFFFFu, A);
-      hist_count_all(subr, w[k] >> 16, A);
-    }
-  }
-}
-
-// Counts symbols [s_lo, s_hi) into the lane's replica `subr` of the LDS
-// window: scalar head up to the first 16-byte boundary, 16-byte vectors
-// (four in flight per lane), scalar tail.  ALL: the window is the whole
-// alphabet plus a trash bin (lo = 0, W = A); otherwise symbols outside
-// [lo, lo + W) are skipped.
-template <int SB, bool ALL>
-__device__ __forceinline__ void hist_range(uint32_t* subr, const void* __restrict__ sym, uint64_t s_lo,
-                                           uint64_t s_hi, uint32_t lo, uint32_t W, uint32_t A, bool& bad) {
-  constexpr uint32_t kPerVec = 16 / SB;
-  const uint32_t tid = threadIdx.x;
-  const uintptr_t addr = (uintptr_t)sym + s_lo * SB;
-  uint64_t head = ((16 - (addr & 15)) & 15) / SB;
-  if (head > s_hi - s_lo) head = s_hi - s_lo;
-  const uint64_t nvec = (s_hi - s_lo - head) / kPerVec;
-  const uint4* body = (const uint4*)((const char*)sym + (s_lo + head) * SB);
-  uint64_t v = tid;
-  constexpr int kUnroll = 4;
-  for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < nvec; v += kUnroll * (uint64_t)blockDim.x) {
-    uint4 q[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      if (ALL) hist_count_vec_all<SB>(subr, q[u], A);
-      else hist_count_vec<SB>(subr, q[u], lo, W, A, bad);
-    }
-  }
-  for (; v < nvec; v += blockDim.x) {
-    if (ALL) hist_count_vec_all<SB>(subr, body[v], A);
-    else hist_count_vec<SB>(subr, body[v], lo, W, A, bad);
-  }
-  for (uint64_t i = tid; i < head; i += blockDim.x) {
-    if (ALL) hist_count_all(subr, sym_load<SB>(sym, s_lo + i), A);
-    else hist_count(subr, sym_load<SB>(sym, s_lo + i), lo, W, A, bad);
-  }
-  for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x) {
-    if (ALL) hist_count_all(subr, sym_load<SB>(sym, i), A);
-    else hist_count(subr, sym_load<SB>(sym, i), lo, W, A, bad);
-  }
-}
-
-// Words of LDS a window needs: R replicas, hist_stride words apart.
-__host__ __device__ inline uint32_t hist_window_words(uint32_t W, uint32_t A, uint32_t R) {
-  return hist_stride(W, A) * R;
 }
 
 // One launch counts bins [lo, lo + W).  Workgroup w takes the contiguous
@@ -223,56 +116,23 @@ hipError_t launch_slab_hist_reduce(const uint32_t* slab_hist, uint32_t nslabs, u
   return hipGetLastError();
 }
 
-// Batched stage 1: workgroup i counts slab g of stream s for the work item
-// items[i] = streams[s].item0 + g and stores the slab's counts.  The LDS
-// holds lds_words words: as many interleaved replicas of the alphabet as fit.
+// Batched stage 1: workgroup i counts the slab of work item items[i].
 __global__ __launch_bounds__(kHistThreads) void batch_histogram_kernel(const BatchStream* __restrict__ streams,
                                                                        const uint32_t* __restrict__ item_stream,
                                                                        const uint32_t* __restrict__ items,
                                                                        uint32_t lds_words) {
   extern __shared__ uint32_t sub[];
   const uint32_t item = items[blockIdx.x];
-  const uint32_t s = item_stream[item];
-  const BatchStream& bs = streams[s];
-  const uint32_t g = item - bs.item0;
-  const uint32_t A = bs.A;
-  const uint32_t Wp = hist_stride(A, A);
-  uint32_t R = 1;
-  while (R < 16 && Wp * R * 2 <= lds_words) R *= 2;
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < Wp * R; i += blockDim.x) sub[i] = 0;
-  __syncthreads();
-  const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
-  const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
-  bool bad = false;
-  uint32_t* const subr = sub + (tid & (R - 1)) * Wp;
-  if (bs.sym_bytes == 1) hist_range<1, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
-  else hist_range<2, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
-  __syncthreads();
-  uint32_t* row = bs.part + (uint64_t)g * A;
-  for (uint32_t b = tid; b < A; b += blockDim.x) {
-    uint32_t c = 0;
-    for (uint32_t r = 0; r < R; ++r) c += sub[r * Wp + b];
-    row[b] = c;
-  }
-  if (tid < R && sub[tid * Wp + A]) bad = true;
-  if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
+  const BatchStream& bs = streams[item_stream[item]];
+  batch_hist_item(bs, item - bs.item0, sub, lds_words);
 }
 
-// Batched stage 2: workgroup i sums, for stream s = item >> 6 and bins
-// [256 c, 256 c + 256) with c = item & 63, the counts of every slab of s
-// into its histogram (coalesced row segments, one store per bin).
+// Batched stage 2: workgroup i sums bin chunk (items[i] & 63) of stream
+// items[i] >> 6.
 __global__ __launch_bounds__(kBatchReduceBins) void batch_hist_reduce_kernel(const BatchStream* __restrict__ streams,
                                                                              const uint32_t* __restrict__ items) {
   const uint32_t item = items[blockIdx.x];
-  const BatchStream& bs = streams[item >> 6];
-  const uint32_t b = (item & 63) * kBatchReduceBins + threadIdx.x;
-  if (b >= bs.A) return;
-  const uint32_t* p = bs.part + b;
-  uint32_t c = 0;
-#pragma unroll 8
-  for (uint32_t g = 0; g < bs.nslabs; ++g) c += p[(uint64_t)g * bs.A];
-  bs.hist[b] = c;
+  batch_reduce_item(streams[item >> 6], item & 63);
 }
 
 hipError_t launch_batch_hist_reduce(const BatchStream* d_streams, const uint32_t* d_red_items, uint32_t nred,

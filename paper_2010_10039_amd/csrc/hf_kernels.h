@@ -78,7 +78,7 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
 
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.
-size_t codebook_workspace_bytes(uint32_t alphabet);
+size_t codebook_workspace_bytes(uint32_t alphabet, uint32_t tree_cap = kCbLdsMaxUsed);
 
 hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
                            uint32_t* status, hipStream_t stream, const KernelTimer& timer);
@@ -118,6 +118,25 @@ struct BatchStream {
   uint64_t* offsets;
   uint32_t* status;
 };
+
+// Arguments of the persistent batched launch (every stage in one kernel).
+struct FusedArgs {
+  const BatchStream* streams;
+  const uint32_t* item_stream;  // [nitems] stream of every (stream, slab) item
+  const uint32_t* hist_items;   // [nitems] queue order of the slab histograms
+  const uint32_t* red_items;    // [nred] stream << 6 | bin chunk
+  const uint32_t* enc_items;    // [nitems] queue order of the slab encodings
+  uint32_t nitems, nred, nstreams;
+  uint32_t lds_words;  // dynamic LDS words (the histogram's replicas)
+  uint32_t* sync;      // [1 + 4 nstreams], zero: queue head, then per-stream counters
+};
+// Codebook tree kept in LDS up to this many used symbols in the persistent
+// launch (beyond it, the stream's cb_ws).
+constexpr uint32_t kFusedTreeCap = 1024;
+// Dynamic LDS of the persistent launch: the largest need of any stage of any
+// stream (host array of the streams' descriptors).
+size_t batch_persistent_lds_bytes(const BatchStream* streams, uint32_t nstreams);
+hipError_t launch_batch_persistent(const FusedArgs& f, size_t lds_bytes, int num_cus, hipStream_t stream);
 
 // Histogram LDS words for a batch group whose alphabets are at most A.
 uint32_t batch_hist_lds_words(uint32_t max_alphabet);

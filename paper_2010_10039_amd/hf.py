@@ -437,6 +437,8 @@ _lib.hf_batch_workspace_bytes.argtypes = [ctypes.POINTER(hf_stream_desc), _U32]
 _lib.hf_batch_workspace_bytes.restype = _SZ
 _lib.hf_encode_batch.argtypes = [ctypes.POINTER(hf_stream_desc), _U32, _P, _SZ, _P, _P]
 _lib.hf_encode_batch.restype = ctypes.c_int
+_lib.hf_encode_batch_persistent.argtypes = [ctypes.POINTER(hf_stream_desc), _U32, _P, _SZ, _P, _P]
+_lib.hf_encode_batch_persistent.restype = ctypes.c_int
 
 
 def hf_batch_workspace_bytes(descs) -> int:
@@ -447,6 +449,12 @@ def hf_encode_batch(descs, ws: torch.Tensor, status: torch.Tensor) -> None:
     """Encode every stream of the ctypes hf_stream_desc array `descs`."""
     _check(_lib.hf_encode_batch(descs, len(descs), _ptr(ws), ws.numel(), _ptr(status), _stream()),
            "hf_encode_batch")
+
+
+def hf_encode_batch_persistent(descs, ws: torch.Tensor, status: torch.Tensor) -> None:
+    """hf_encode_batch in one persistent launch (same arguments, same results)."""
+    _check(_lib.hf_encode_batch_persistent(descs, len(descs), _ptr(ws), ws.numel(), _ptr(status), _stream()),
+           "hf_encode_batch_persistent")
 
 
 class BatchEncoder:
@@ -491,6 +499,7 @@ class BatchEncoder:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.status = torch.zeros(n, dtype=torch.int32, device=device)
 
-    def run(self):
-        hf_encode_batch(self.descs, self.ws, self.status)
+    def run(self, persistent: bool = False):
+        """Encodes the batch: one launch per stage, or one persistent launch."""
+        (hf_encode_batch_persistent if persistent else hf_encode_batch)(self.descs, self.ws, self.status)
         return self.outs, self.offsets

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ("hf_histogram", "hf_build_codebook", "hf_encode", "hf_decode", "hf_decode_check",
                  "hf_lorenzo_histogram", "hf_workspace_bytes", "hf_decode_workspace_bytes", "hf_bound_words",
-                 "hf_encode_noalloc"):
+                 "hf_encode_noalloc", "hf_encode_batch_persistent"):
         assert want in names
 
 
