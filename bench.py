@@ -49,6 +49,9 @@ def parse():
                         "frontend: from the 512^3 float field, fused quantization + Lorenzo + histogram, "
                         "then codebook and encode; "
                         "paperformat: the paper's ReduceShuffleMerge<M,r> format, swept over M x r (Table 3's shape)")
+    p.add_argument("--graph", action="store_true",
+                   help="pipeline mode: time replays of the whole pass captured as one HIP graph (small "
+                        "streams are bound by per-launch host overhead); stage times then come from eager steps")
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     p.add_argument("--rho", default="0.5,0.8",
                    help="serve mode: offered loads as fractions of the measured saturated capacity")
@@ -891,18 +894,28 @@ def main():
 
     # Timed steps: an event pair around each encode kernel (the roofline's
     # per-launch duration); the other stages carry no event packets here.
+    # With --graph the timed steps are replays of one captured pass and every
+    # stage's kernel is timed in separate eager steps.
+    graph = enc.capture(d) if args.graph else None
     ev = timer_events(("encode",), args.steps)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record()
     for k in range(args.steps):
-        enc.run(d, timers={"encode": ev["encode"][k]})
+        if graph is not None:
+            graph.replay()
+        else:
+            enc.run(d, timers={"encode": ev["encode"][k]})
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     hf.raise_on_status(enc.status, "timed steps")
     ms_per_step = start.elapsed_time(stop) / args.steps
+    if graph is not None:
+        for k in range(args.steps):
+            enc.run(d, timers={"encode": ev["encode"][k]})
+        torch.cuda.synchronize()
     stage_ms = {"encode": sum(a.elapsed_time(b) for a, b in ev["encode"]) / args.steps}
     # the other stages' main kernels, timed in separate (untimed) steps
     ev_other = timer_events(("hist", "codebook"), args.steps)
@@ -917,7 +930,10 @@ def main():
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nmed)]
     for a, b in pairs:
         a.record()
-        enc.run(d)
+        if graph is not None:
+            graph.replay()
+        else:
+            enc.run(d)
         b.record()
     torch.cuda.synchronize()
     median_us = float(np.median([a.elapsed_time(b) for a, b in pairs])) * 1e3
@@ -988,6 +1004,7 @@ def main():
             "median_step_us": round(median_us, 2),
             "median_steps": nmed,
             "device_copy_gbs": round(copy_gbs, 1),
+            "graph": bool(args.graph),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -416,6 +416,21 @@ class Encoder:
                   self.nslabs, self.slab_hist)
         return self.out, self.offsets
 
+    def capture(self, sym: torch.Tensor):
+        """One pass of the whole path over `sym` captured as a HIP graph
+        (torch.cuda.CUDAGraph): replay() then launches every kernel of the
+        pass at once, which removes the per-launch host overhead that bounds
+        small streams.  Every kernel writes or clears what it reads (no
+        memset nodes), so each replay gives the eager result; the graph
+        keeps using this encoder's buffers and `sym`'s storage."""
+        assert sym.numel() == self.n
+        self.run(sym)  # one eager pass first: one-time host set-up happens outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(sym)
+        return g
+
 
 class hf_stream_desc(ctypes.Structure):
     _fields_ = [
