@@ -108,14 +108,19 @@ __global__ __launch_bounds__(kDecThreads) void decode_check_kernel(
 // so a code's length is lo + #{l in [lo, hi) : W < LJ[l]} for any bounds
 // lo <= l <= hi; a table of every kPeek-bit prefix gives those bounds (and
 // the symbol itself for codes of at most kPeek bits).
+// Sizing: two 1024-lane workgroups share a CU (8 waves per SIMD, which caps
+// the kernel at 64 VGPRs), so the per-wave LDS is small: a 1024-symbol
+// output tile, segments of about 7/8 of it, regions of at most 96 bits.
+// The decoder is issue- and latency-bound (three decodes per code), so the
+// extra waves in flight matter more than longer segments would.
 constexpr uint32_t kPeek = 12;
-constexpr int kDWG = 512;                           // threads of a decoder workgroup
+constexpr int kDWG = 1024;                          // threads of a decoder workgroup
 constexpr int kDWaves = kDWG / kWave;
-constexpr uint32_t kTile = 2048;                    // symbols per output round of a wave
-constexpr uint32_t kMaxRegion = 128;                // bits of one lane's region, at most
+constexpr uint32_t kTile = 1024;                    // symbols per output round of a wave
+constexpr uint32_t kSegSyms = kTile * 7 / 8;        // symbols a segment aims at
+constexpr uint32_t kMaxRegion = 96;                 // bits of one lane's region, at most
 constexpr uint32_t kWinWords = 2 * kMaxRegion + 8;  // stream words staged per segment
 constexpr uint32_t kMapWords = 2 * kMaxRegion + 4;  // code-start bitmap words
-constexpr uint32_t kRevLds = 4096;                  // reverse book copied to LDS up to this many codes
 constexpr uint32_t kTabShort = 1u << 30;            // table entry: the symbol is in bits [0, 16)
 
 template <int SB>
@@ -128,7 +133,7 @@ constexpr uint32_t wave_words() {
 }
 template <int SB>
 constexpr size_t decode_lds_bytes() {
-  return ((size_t)(1u << kPeek) + kRevLds / 2 + (size_t)kDWaves * wave_words<SB>()) * 4;
+  return ((size_t)(1u << kPeek) + (size_t)kDWaves * wave_words<SB>()) * 4;
 }
 
 // Prefix table: entry p describes the windows whose first kPeek bits are p.
@@ -186,7 +191,7 @@ struct DecArgs {
 // Per-workgroup tables in LDS.
 struct DecShared {
   uint64_t first[HF_MAX_CODELEN + 1];
-  uint64_t lj[HF_MAX_CODELEN + 1];  // First[l] << (64 - l)
+  uint64_t lj[HF_MAX_CODELEN + 4];  // First[l] << (64 - l); 0 past the longest length
   uint32_t entry[HF_MAX_CODELEN + 1];
   uint32_t cnt[HF_MAX_CODELEN + 1];
   uint32_t gcd;
@@ -212,7 +217,11 @@ __device__ __forceinline__ uint64_t dec_window(const uint32_t* win, uint32_t p) 
 __device__ __forceinline__ uint32_t dec_len(uint32_t t, uint64_t W, const uint64_t* lj) {
   const uint32_t lo = (t >> 16) & 127u, hi = (t >> 23) & 127u;
   uint32_t len = lo;
-  for (uint32_t l = lo; l < hi; ++l) len += W < lj[l] ? 1u : 0u;
+  // four bounds per pass, so a long code waits on one LDS round trip per four
+  // lengths: W >= LJ[l] for every l >= hi (LJ is non-increasing), so the terms
+  // past hi add nothing
+  for (uint32_t l = lo; l < hi; l += 4)
+    len += (W < lj[l] ? 1u : 0u) + (W < lj[l + 1] ? 1u : 0u) + (W < lj[l + 2] ? 1u : 0u) + (W < lj[l + 3] ? 1u : 0u);
   return len;
 }
 
@@ -260,21 +269,19 @@ __device__ __forceinline__ void tile_copy_out(const uint32_t* tile, uint32_t h, 
 }
 
 template <int SB>
-__global__ __launch_bounds__(kDWG) void decode_kernel(DecArgs a) {
+__global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void decode_kernel(DecArgs a) {
   extern __shared__ __align__(16) uint32_t dlds[];
   __shared__ DecShared ds;
   const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   uint32_t* const tab = dlds;
-  uint16_t* const rev16 = (uint16_t*)(dlds + (1u << kPeek));
-  uint32_t* const tile = dlds + (1u << kPeek) + kRevLds / 2 + wv * wave_words<SB>();
+  uint32_t* const tile = dlds + (1u << kPeek) + wv * wave_words<SB>();
   uint32_t* const win = tile + tile_words<SB>();
   uint32_t* const map = win + kWinWords;
 
   const uint32_t m = (uint32_t)a.info[0];
   for (uint32_t i = tid; i < (1u << kPeek) / 4; i += kDWG) ((uint4*)tab)[i] = ((const uint4*)a.gtab)[i];
-  const bool rev_lds = m <= kRevLds;
-  if (rev_lds)
-    for (uint32_t i = tid; i < m; i += kDWG) rev16[i] = (uint16_t)a.rev[i];
+  for (uint32_t l = tid; l < HF_MAX_CODELEN + 4; l += kDWG)
+    if (l > HF_MAX_CODELEN) ds.lj[l] = 0;
   for (uint32_t l = tid; l <= HF_MAX_CODELEN; l += kDWG) {
     const uint64_t f = a.first[l];
     ds.first[l] = f;
@@ -309,8 +316,8 @@ __global__ __launch_bounds__(kDWG) void decode_kernel(DecArgs a) {
     const uint64_t i0 = k << a.chunk_log2;
     const uint32_t ns = (uint32_t)min(a.n - i0, 1ull << a.chunk_log2);
     bool bad = b1 < b0 || b1 > total_bits;
-    // region size: about kTile * 3/4 symbols per segment at this chunk's bits per symbol
-    uint64_t S64 = bad ? 1 : (b1 - b0) * (kTile * 3 / 4 / kWave) / ns;
+    // region size: about kSegSyms symbols per segment at this chunk's bits per symbol
+    uint64_t S64 = bad ? 1 : (b1 - b0) * (kSegSyms / kWave) / ns;
     const uint32_t S = (uint32_t)max(1ull, min((uint64_t)kMaxRegion, S64));
     uint64_t seg = b0;  // a true code boundary
     uint32_t done = 0;  // symbols of the chunk written
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(kDWG) void decode_kernel(DecArgs a) {
               ok = v >= f && v - f < ds.cnt[len];
               if (ok) {
                 const uint32_t idx = ds.entry[len] + (uint32_t)(v - f);
-                sym = rev_lds ? rev16[idx] : a.rev[idx];
+                sym = a.rev[idx];  // codes longer than the table's prefix are rare
               }
             }
             if (!ok) {
