@@ -293,8 +293,9 @@ __device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint3
 // bit's ballot or its complement; a key goes to its digit's offset plus the
 // equal-digit lanes before it (so equal counts keep their order), and the
 // last of them advances the offset.  A wave's LDS operations take effect
-// in order, so the next group sees the advanced offsets.  The next 64 keys
-// are loaded while the current ones are placed.
+// in order, so the next group sees the advanced offsets.  Keys are read
+// four groups ahead (the workspace's latency, not the placing, bounds a
+// lone workgroup's pass).
 template <int NT>
 __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, uint32_t m, uint32_t wmax,
                                                 Shared& sh, uint32_t* cnt) {
@@ -312,12 +313,19 @@ __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, ui
     const uint32_t shift = 16 + 8 * p;
     for (uint32_t i = tid; i < NW * 256; i += NT) cnt[i] = 0;
     __syncthreads();
+    // four groups of 64 keys are counted while the next four load
+    uint64_t k[4], kn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = s0 + u * kWave + lane;
+      kn[u] = i < s1 ? src[i] : 0ull;
+    }
     for (uint32_t i0 = s0; i0 < s1; i0 += 4 * kWave) {
-      uint64_t k[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const uint32_t i = i0 + u * kWave + lane;
-        k[u] = i < s1 ? src[i] : 0ull;
+        k[u] = kn[u];
+        const uint32_t i = i0 + (4 + u) * kWave + lane;
+        kn[u] = i < s1 ? src[i] : 0ull;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -343,23 +351,36 @@ __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, ui
       pre += v[q];
     }
     __syncthreads();
-    uint64_t kn = s0 + lane < s1 ? src[s0 + lane] : 0ull;
-    for (uint32_t b = s0; b < s1; b += kWave) {
-      const bool valid = b + lane < s1;
-      const uint64_t k = kn;
-      if (b + kWave + lane < s1) kn = src[b + kWave + lane];
-      const uint32_t d = valid ? (uint32_t)(k >> shift) & 255 : 256u;  // 256: no used digit
-      uint64_t match = ~0ull;
+    // four groups are placed while the next four load
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const bool on = (d >> q) & 1u;
-        const uint64_t B = __ballot(on);
-        match &= on ? B : ~B;
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = s0 + u * kWave + lane;
+      kn[u] = i < s1 ? src[i] : 0ull;
+    }
+    for (uint32_t b0 = s0; b0 < s1; b0 += 4 * kWave) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        k[u] = kn[u];
+        const uint32_t i = b0 + (4 + u) * kWave + lane;
+        kn[u] = i < s1 ? src[i] : 0ull;
       }
-      if (valid) {
-        const uint32_t slot = wc[d] + (uint32_t)__popcll(match & lanemask_lt());
-        dst[slot] = k;
-        if ((match >> lane) == 1ull) wc[d] = slot + 1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t b = b0 + u * kWave;
+        const bool valid = b + lane < s1;
+        const uint32_t d = valid ? (uint32_t)(k[u] >> shift) & 255 : 256u;  // 256: no used digit
+        uint64_t match = ~0ull;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const bool on = (d >> q) & 1u;
+          const uint64_t B = __ballot(on);
+          match &= on ? B : ~B;
+        }
+        if (valid) {
+          const uint32_t slot = wc[d] + (uint32_t)__popcll(match & lanemask_lt());
+          dst[slot] = k[u];
+          if ((match >> lane) == 1ull) wc[d] = slot + 1;
+        }
       }
     }
     __syncthreads();
@@ -372,70 +393,13 @@ __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, ui
   }
 }
 
-// lds_scratch: NT / 64 * 256 words of LDS free until the rounds.
+// Steps 3 and 4 of a book: the GenerateCL rounds over the sorted leaves
+// t.key[0, m) (m >= 2) and the depth of every internal node; returns the
+// array that holds the depths (one of t.dA, t.dB).
 template <typename IdT, int NT>
-__device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
-                                           uint32_t A, uint32_t m, uint32_t wmax, const hf_codebook& book,
-                                           uint32_t* status, uint32_t* lds_scratch) {
-  constexpr int NW = NT / kWave;
+__device__ __forceinline__ uint16_t* build_book_tree(const Tree<IdT>& t, Shared& sh, uint32_t m, uint32_t* status) {
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
-
-  // ---- 1. compaction -----------------------------------------------------
-  compact<NT>(hist, A, t.key, t.usym, book, sh.wtot);
-  for (uint32_t l = tid; l <= kMaxLen; l += NT) sh.cnt[l] = 0;
-  if (tid == 0) {
-    sh.total = 0;
-    sh.lmax = 0;
-    sh.lmin = 0xFFFFFFFFu;
-  }
-  __syncthreads();
-
-  if (m <= 1) {
-    // no tree: an empty book, or one symbol with the 1-bit code 0
-    for (uint32_t l = tid; l <= kMaxLen; l += NT) {
-      book.first[l] = 0;
-      book.entry[l] = (m == 1 && l >= 2) ? 1u : 0u;
-    }
-    if (tid == 0) {
-      uint64_t h0 = 0;
-      if (m == 1) {
-        const uint32_t s = (uint32_t)t.usym[0];
-        h0 = t.key[0] >> 16;
-        book.cl[s] = 1;
-        book.cw[s] = 0;
-        book.rev[0] = s;
-      }
-      book.info[0] = m;
-      book.info[1] = m;
-      book.info[2] = h0;
-      book.info[3] = m;
-    }
-    return;
-  }
-
-  // ---- 2. sort leaves ascending by (count, u) --------------------------------
-  if (m <= 512) {
-    // rank sort: keys are distinct (u in the low bits); broadcast reads
-    for (uint32_t i = tid; i < m; i += NT) {
-      const uint64_t k = t.key[i];
-      uint32_t r = 0;
-      uint32_t j = 0;
-      for (; j + 4 <= m; j += 4) {
-        const uint64_t k0 = t.key[j], k1 = t.key[j + 1], k2 = t.key[j + 2], k3 = t.key[j + 3];
-        r += (k0 < k) + (k1 < k) + (k2 < k) + (k3 < k);
-      }
-      for (; j < m; ++j) r += t.key[j] < k;
-      t.mw[r] = k;
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < m; i += NT) t.key[i] = t.mw[i];
-  } else {
-    radix_sort_keys<NT>(t.key, t.mw, m, wmax, sh, lds_scratch);
-  }
-  __syncthreads();
-
   // ---- 3. GenerateCL rounds ------------------------------------------------
   uint32_t nrounds = kRoundEndsMax + 1;  // rounds run by the workgroup (recorded up to kRoundEndsMax)
   if (sizeof(IdT) == 2 && m <= kOneWaveRoundsMax) {
@@ -595,27 +559,110 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     }
   }
   }
+  return dc;
+}
+
+// lds_scratch: NT / 64 * 256 words of LDS free until the rounds.
+template <typename IdT, int NT>
+__device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
+                                           uint32_t A, uint32_t m, uint32_t wmax, const hf_codebook& book,
+                                           uint32_t* status, uint32_t* lds_scratch) {
+  constexpr int NW = NT / kWave;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t wave = tid / kWave;
+
+  // ---- 1. compaction -----------------------------------------------------
+  compact<NT>(hist, A, t.key, t.usym, book, sh.wtot);
+  for (uint32_t l = tid; l <= kMaxLen; l += NT) sh.cnt[l] = 0;
+  if (tid == 0) {
+    sh.total = 0;
+    sh.lmax = 0;
+    sh.lmin = 0xFFFFFFFFu;
+  }
+  __syncthreads();
+
+  if (m <= 1) {
+    // no tree: an empty book, or one symbol with the 1-bit code 0
+    for (uint32_t l = tid; l <= kMaxLen; l += NT) {
+      book.first[l] = 0;
+      book.entry[l] = (m == 1 && l >= 2) ? 1u : 0u;
+    }
+    if (tid == 0) {
+      uint64_t h0 = 0;
+      if (m == 1) {
+        const uint32_t s = (uint32_t)t.usym[0];
+        h0 = t.key[0] >> 16;
+        book.cl[s] = 1;
+        book.cw[s] = 0;
+        book.rev[0] = s;
+      }
+      book.info[0] = m;
+      book.info[1] = m;
+      book.info[2] = h0;
+      book.info[3] = m;
+    }
+    return;
+  }
+
+  // ---- 2. sort leaves ascending by (count, u) --------------------------------
+  if (m <= 512) {
+    // rank sort: keys are distinct (u in the low bits); broadcast reads
+    for (uint32_t i = tid; i < m; i += NT) {
+      const uint64_t k = t.key[i];
+      uint32_t r = 0;
+      uint32_t j = 0;
+      for (; j + 4 <= m; j += 4) {
+        const uint64_t k0 = t.key[j], k1 = t.key[j + 1], k2 = t.key[j + 2], k3 = t.key[j + 3];
+        r += (k0 < k) + (k1 < k) + (k2 < k) + (k3 < k);
+      }
+      for (; j < m; ++j) r += t.key[j] < k;
+      t.mw[r] = k;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < m; i += NT) t.key[i] = t.mw[i];
+  } else {
+    radix_sort_keys<NT>(t.key, t.mw, m, wmax, sh, lds_scratch);
+  }
+  __syncthreads();
+
+  uint16_t* dc = build_book_tree<IdT, NT>(t, sh, m, status);
 
   // ---- 5a. leaf lengths, counts per length, total bits ----------------------
   uint64_t bits = 0;
   uint32_t my_max = 0, my_min = 0xFFFFFFFFu;
-#pragma unroll 2
-  for (uint32_t i0 = 0; i0 < m; i0 += NT) {
-    const uint32_t i = i0 + tid;
-    const bool valid = i < m;
-    uint32_t l = 0;
-    if (valid) {
-      const uint64_t kk = t.key[i];
-      const uint32_t u = (uint32_t)(kk & 0xFFFFu);
-      l = (uint32_t)dc[t.par[i]] + 1;
-      bits += (kk >> 16) * l;
-      my_max = max(my_max, l);
-      my_min = min(my_min, l);
-      if (l > kMaxLen) l = kMaxLen;  // flagged below; keeps indexes in range
-      t.clu[u] = (uint8_t)l;
-      book.cl[(uint32_t)t.usym[u]] = (uint8_t)l;
+  // four leaves a lane at a time, every load issued before the first store
+  // (the stores may alias the loads as far as the compiler knows)
+  for (uint32_t i0 = 0; i0 < m; i0 += 4 * NT) {
+    uint64_t kk[4];
+    uint32_t pr[4], dd[4], sy[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t i = i0 + v * NT + tid;
+      kk[v] = i < m ? t.key[i] : 0ull;
+      pr[v] = i < m ? (uint32_t)t.par[i] : 0u;
     }
-    count_lengths(l, valid, sh.cnt);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const bool valid = i0 + v * NT + tid < m;
+      dd[v] = valid ? (uint32_t)dc[pr[v]] : 0u;
+      sy[v] = valid ? (uint32_t)t.usym[(uint32_t)(kk[v] & 0xFFFFu)] : 0u;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const bool valid = i0 + v * NT + tid < m;
+      uint32_t l = 0;
+      if (valid) {
+        l = dd[v] + 1;
+        bits += (kk[v] >> 16) * l;
+        my_max = max(my_max, l);
+        my_min = min(my_min, l);
+        if (l > kMaxLen) l = kMaxLen;  // flagged below; keeps indexes in range
+        t.clu[(uint32_t)(kk[v] & 0xFFFFu)] = (uint8_t)l;
+        book.cl[sy[v]] = (uint8_t)l;
+      }
+      count_lengths(l, valid, sh.cnt);
+    }
   }
   bits = wave_sum_u64(bits);
   my_max = wave_max_u32(my_max);
@@ -668,26 +715,44 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   uint32_t* wc = sh.cntw[wave];  // [kMaxLen + 1] this wave's count, then next slot, per length
   for (uint32_t l = lane; l <= kMaxLen; l += kWave) wc[l] = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (uint32_t u0 = sbeg; u0 < send; u0 += kWave) {
-      const uint32_t u = u0 + lane;
-      const bool valid = u < send;
-      const uint32_t l = valid ? t.clu[u] : 0u;
-      uint64_t eq = ~0ull;
+    // four groups are ranked while the next four load
+    uint32_t lv[4], sv[4], ln[4], sn[4];
 #pragma unroll
-      for (int bit = 0; bit < 7; ++bit) {
-        const bool on = (l >> bit) & 1u;
-        const uint64_t B = __ballot(on);
-        eq &= on ? B : ~B;
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t u = sbeg + v * kWave + lane;
+      ln[v] = u < send ? (uint32_t)t.clu[u] : 0u;
+      sn[v] = (pass == 1 && u < send) ? (uint32_t)t.usym[u] : 0u;
+    }
+    for (uint32_t u0 = sbeg; u0 < send; u0 += 4 * kWave) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        lv[v] = ln[v];
+        sv[v] = sn[v];
+        const uint32_t u = u0 + (4 + v) * kWave + lane;
+        ln[v] = u < send ? (uint32_t)t.clu[u] : 0u;
+        sn[v] = (pass == 1 && u < send) ? (uint32_t)t.usym[u] : 0u;
       }
-      const bool last = valid && (eq >> lane) == 1ull;
-      if (pass == 0) {
-        if (last) wc[l] += (uint32_t)__popcll(eq);
-      } else if (valid) {
-        const uint32_t pos = wc[l] + (uint32_t)__popcll(eq & lanemask_lt());
-        const uint32_t s = (uint32_t)t.usym[u];
-        book.rev[pos] = s;
-        book.cw[s] = sh.first[l] + (pos - sh.entry[l]);
-        if (last) wc[l] = pos + 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool valid = u0 + v * kWave + lane < send;
+        const uint32_t l = valid ? lv[v] : 0u;
+        uint64_t eq = ~0ull;
+#pragma unroll
+        for (int bit = 0; bit < 7; ++bit) {
+          const bool on = (l >> bit) & 1u;
+          const uint64_t B = __ballot(on);
+          eq &= on ? B : ~B;
+        }
+        const bool last = valid && (eq >> lane) == 1ull;
+        if (pass == 0) {
+          if (last) wc[l] += (uint32_t)__popcll(eq);
+        } else if (valid) {
+          const uint32_t pos = wc[l] + (uint32_t)__popcll(eq & lanemask_lt());
+          const uint32_t s = sv[v];
+          book.rev[pos] = s;
+          book.cw[s] = sh.first[l] + (pos - sh.entry[l]);
+          if (last) wc[l] = pos + 1;
+        }
       }
     }
     if (pass == 0) {

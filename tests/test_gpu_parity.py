@@ -240,6 +240,28 @@ def _hist_cases():
     h = np.zeros(16384, np.uint32)
     h[rng.choice(16384, size=6000, replace=False)] = np.maximum(1, (1e9 * 0.9975 ** np.arange(6000))).astype(np.uint32)
     cases["m6000_geom_global"] = h
+    # alphabets above 8192: the grid-wide sort, lengths and codewords when more
+    # than 4096 symbols are used, else the single-workgroup build
+    h = np.zeros(16384, np.uint32)
+    h[rng.choice(16384, size=4097, replace=False)] = rng.integers(1, 1000, size=4097)
+    cases["multi_m4097_a16384"] = h
+    h = np.zeros(32768, np.uint32)
+    h[rng.choice(32768, size=4096, replace=False)] = rng.integers(1, 1000, size=4096)
+    cases["multi_fallback_m4096_a32768"] = h
+    h = np.zeros(10000, np.uint32)
+    h[rng.choice(10000, size=9000, replace=False)] = rng.integers(1, 1 << 20, size=9000)
+    cases["multi_a10000_m9000"] = h
+    h = np.zeros(16384, np.uint32)
+    h[rng.choice(16384, size=6000, replace=False)] = rng.integers(1, 1 << 31, size=6000)
+    cases["multi_counts_to_2^31"] = h
+    h = np.zeros(20000, np.uint32)
+    pos = rng.choice(20000, size=4200, replace=False)
+    h[pos[:40]] = _fib(40)
+    h[pos[40:]] = 1
+    cases["multi_fib40_long_codes"] = h
+    h = np.zeros(65536, np.uint32)
+    h[rng.choice(65536, size=5000, replace=False)] = rng.choice(np.array([1, 2, 2, 3, 7], np.uint32), size=5000)
+    cases["multi_ties_m5000_a65536"] = h
     # the sum of counts just below / at 2^32 - 1 (register path / general path)
     h = np.zeros(1024, np.uint32); h[:200] = 1; h[500] = 0xFFFFFFFE - 200 - 7; h[501:508] = 1
     assert int(h.sum(dtype=np.uint64)) == 0xFFFFFFFE
