@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
     p.add_argument("--mode", choices=("pipeline", "copy", "batch", "serve", "decode", "frontend", "paperformat",
-                                      "cpu"),
+                                      "cpu", "codebook"),
                    default="pipeline",
                    help="copy: only time a device-to-device copy of the input (bandwidth calibration); "
                         "batch: 512 independent streams per step, batched vs one plain pass per stream; "
@@ -48,7 +48,8 @@ def parse():
                         "decode: hf_decode of the workload's encoded stream; "
                         "frontend: from the 512^3 float field, fused quantization + Lorenzo + histogram, "
                         "then codebook and encode; "
-                        "paperformat: the paper's ReduceShuffleMerge<M,r> format, swept over M x r (Table 3's shape)")
+                        "paperformat: the paper's ReduceShuffleMerge<M,r> format, swept over M x r (Table 3's shape); "
+                        "codebook: hf_build_codebook time against alphabet size (Table 2's shape)")
     p.add_argument("--graph", action="store_true",
                    help="pipeline mode: time replays of the whole pass captured as one HIP graph (small "
                         "streams are bound by per-launch host overhead); stage times then come from eager steps")
@@ -206,6 +207,48 @@ def run_cpu(args):
         log(f"threads {t}: " + ", ".join(f"{k}={v}" for k, v in enc[-1].items()))
     return {"mode": "cpu", "workload": args.workload, "threads_max": maxt, "codebook_table5": codebook,
             "encoder_table6": enc}
+
+
+def run_codebook(args):
+    """Table 2 analog on the GPU: hf_build_codebook time against the number
+    of symbols.  Synthetic normal histograms (the paper's stand-in for
+    alphabets larger than its datasets') and Zipf(1.1) counts with every
+    symbol used; each book is checked against the oracle before it is
+    timed.  Alphabets above 8192 take the grid-wide sort and tail when more
+    than 4096 symbols are used."""
+    import torch
+
+    import oracle
+    from paper_2010_10039_amd import hf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    steps = max(3, min(args.steps, 30))
+    rows = []
+    for A in (1024, 2048, 4096, 8192, 16384, 32768, 65536):
+        for kind in ("normal", "zipf"):
+            if kind == "normal":
+                h = workloads.skewed_histogram(A, 1 << 24, seed=1)
+            else:
+                rng = np.random.default_rng(A)
+                p = np.arange(1, A + 1, dtype=np.float64) ** -1.1
+                h = rng.multinomial(1 << 28, p / p.sum())[rng.permutation(A)].astype(np.uint32)
+                h[h == 0] = 1
+            hd = torch.from_numpy(h.view(np.int32)).cuda()
+            ws = hf.new_workspace(1, A)
+            status = hf.new_status()
+            book = hf.hf_build_codebook(hd, ws=ws, status=status)
+            torch.cuda.synchronize()
+            hf.raise_on_status(status, "codebook")
+            ref = oracle.codebook(h)
+            if not (np.array_equal(book.cl.cpu().numpy(), ref.cl) and
+                    np.array_equal(book.cw.cpu().numpy().view(np.uint64), ref.cw)):
+                raise SystemExit(f"codebook differs from the oracle's: {kind} A={A}")
+            ms = _timed(lambda _k: hf.hf_build_codebook(hd, book=book, ws=ws, status=status), steps)
+            rows.append({"alphabet": A, "kind": kind, "used": int(np.count_nonzero(h)), "us": round(ms * 1e3, 1)})
+            log(f"codebook {kind} A={A}: {rows[-1]['used']} used, {rows[-1]['us']} us")
+    return {"mode": "codebook", "metric": "codebook build time", "unit": "us", "higher_is_better": False,
+            "steps": steps, "data": "synthetic", "rows": rows}
 
 
 def _timed(fn, steps: int):
@@ -838,6 +881,9 @@ def main():
         return
     if args.mode == "cpu":
         print(json.dumps(run_cpu(args)), flush=True)
+        return
+    if args.mode == "codebook":
+        print(json.dumps(run_codebook(args)), flush=True)
         return
 
     import torch
