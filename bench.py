@@ -246,9 +246,42 @@ def run_codebook(args):
                 raise SystemExit(f"codebook differs from the oracle's: {kind} A={A}")
             ms = _timed(lambda _k: hf.hf_build_codebook(hd, book=book, ws=ws, status=status), steps)
             rows.append({"alphabet": A, "kind": kind, "used": int(np.count_nonzero(h)), "us": round(ms * 1e3, 1)})
+            rows[-1].update(_codebook_phases(hf, hd, book, ws, status))
             log(f"codebook {kind} A={A}: {rows[-1]['used']} used, {rows[-1]['us']} us")
+    # the books of the pipeline workloads (small: the one-wave path)
+    for name in ("lorenzo3d_512cube_u16_A1024", "zipf_100M_u8_A256", "gaussian_1M_u16_A1024"):
+        A = workloads.WORKLOADS[name]["alphabet"]
+        h = oracle.histogram(workloads.make(name), A)
+        hd = torch.from_numpy(h.view(np.int32)).cuda()
+        ws = hf.new_workspace(1, A)
+        status = hf.new_status()
+        book = hf.hf_build_codebook(hd, ws=ws, status=status)
+        torch.cuda.synchronize()
+        hf.raise_on_status(status, "codebook")
+        ms = _timed(lambda _k: hf.hf_build_codebook(hd, book=book, ws=ws, status=status), steps)
+        rows.append({"alphabet": A, "kind": name, "used": int(np.count_nonzero(h)), "us": round(ms * 1e3, 1)})
+        rows[-1].update(_codebook_phases(hf, hd, book, ws, status))
+        log(f"codebook {name}: {rows[-1]['used']} used, {rows[-1]['us']} us")
     return {"mode": "codebook", "metric": "codebook build time", "unit": "us", "higher_is_better": False,
             "steps": steps, "data": "synthetic", "rows": rows}
+
+
+def _codebook_phases(hf, hd, book, ws, status):
+    """Cycles of each phase of one traced build (median of five); empty for
+    builds whose phases run over the grid."""
+    import torch
+
+    per = []
+    for _ in range(5):
+        stamps = torch.zeros(9, dtype=torch.int64, device="cuda")
+        hf.hf_build_codebook_traced(hd, book, ws, status, stamps)
+        torch.cuda.synchronize()
+        t = stamps.cpu().numpy()
+        if t[0] == 0 or np.any(t[1:] == 0):
+            return {}
+        per.append(np.diff(t))
+    d = np.median(np.array(per), axis=0)
+    return {"phase_cycles": {n: int(v) for n, v in zip(hf.CODEBOOK_PHASES, d)}}
 
 
 def _timed(fn, steps: int):

@@ -199,6 +199,22 @@ hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, voi
                             size_t ws_bytes, uint32_t* d_status, void* stream);
 
 /*
+ * hf_build_codebook with phase timestamps, for profiling the construction
+ * of Sec. 4.2 (Table 2 splits it into code lengths and codewords).  Same
+ * arguments, result and errors; in addition d_stamps (device, uint64[9],
+ * caller-owned) receives the shader clock (s_memtime, core cycles) of the
+ * single-workgroup build as it passes each phase: [0] start, [1] histogram
+ * read and summed, [2] used symbols compacted, [3] sorted, [4] GenerateCL
+ * rounds done, [5] depths, [6] code lengths, [7] First and Entry, [8] end.
+ * Words of phases a build does not pass (no tree for fewer than two used
+ * symbols; alphabets above 8192 with more than 4096 used symbols, whose
+ * sort, lengths and codewords run over the whole grid) keep their
+ * contents: zero them first.  HF_ERR_ARG if d_stamps is NULL.
+ */
+hf_status hf_build_codebook_traced(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
+                                   size_t ws_bytes, uint32_t* d_status, uint64_t* d_stamps, void* stream);
+
+/*
  * Stage 4, encoding (Sec. 4.3): the concatenation, in input order, of the
  * codewords of d_sym[0..n) (MSB of each codeword first), written bit-dense
  * into d_out: bit p of the stream is bit 31 - (p % 32) of d_out[p / 32]; the

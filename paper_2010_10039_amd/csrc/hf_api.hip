@@ -216,6 +216,16 @@ hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, voi
   return launch_result(hf::launch_codebook(d_hist, *book, d_ws, ws_bytes, d_status, (hipStream_t)stream, timer));
 }
 
+hf_status hf_build_codebook_traced(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
+                                   size_t ws_bytes, uint32_t* d_status, uint64_t* d_stamps, void* stream) {
+  const KernelTimer timer = take_timer();
+  if (!d_hist || !valid_book(book) || !d_status || !d_stamps) return HF_ERR_ARG;
+  const size_t need = hf::codebook_workspace_bytes(book->alphabet);
+  if (need > 0 && (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255))) return HF_ERR_WORKSPACE;
+  return launch_result(
+      hf::launch_codebook(d_hist, *book, d_ws, ws_bytes, d_status, (hipStream_t)stream, timer, d_stamps));
+}
+
 hf_status hf_encode(const void* d_sym, uint64_t n, uint32_t sym_bytes, const hf_codebook* book,
                     uint32_t chunk_symbols, uint32_t reduce_log2, uint32_t nslabs,
                     const uint32_t* d_slab_hist, uint32_t* d_out, uint64_t out_capacity_words,

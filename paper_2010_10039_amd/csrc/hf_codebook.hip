@@ -521,10 +521,16 @@ __global__ __launch_bounds__(kMT) void cbm_tail_kernel(hf_codebook book, char* w
 // symbols (multi: the grid-wide steps' state, or null).
 template <int NT>
 __global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict__ hist, hf_codebook book,
-                                                      char* ws, uint32_t* status, const MultiState* multi) {
+                                                      char* ws, uint32_t* status, const MultiState* multi,
+                                                      uint64_t* stamps) {
   if (multi && multi->m > kCbLdsMaxUsed) return;  // built by the grid-wide steps
   __shared__ CbLds lds;
-  codebook_block<NT>(hist, book, ws, status, lds);
+  HF_CB_STAMP(0);
+  codebook_block<NT>(hist, book, ws, status, lds, stamps);
+  if (stamps) {
+    __syncthreads();
+    HF_CB_STAMP(8);
+  }
 }
 
 // Batched stage 3: workgroup s builds stream s's book from its histogram
@@ -547,7 +553,7 @@ size_t codebook_workspace_bytes(uint32_t alphabet, uint32_t tree_cap) {
 }
 
 hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
-                           uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
+                           uint32_t* status, hipStream_t stream, const KernelTimer& timer, uint64_t* stamps) {
   (void)ws_bytes;
   const uint32_t A = book.alphabet;
   char* w = (char*)ws;
@@ -561,11 +567,11 @@ hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* 
       cbm_sort_kernel<<<NB, kMT, 0, stream>>>(hist, book, w, status);
       cbm_tree_kernel<<<1, 1024, 0, stream>>>(book, w, status);
       cbm_tail_kernel<<<NB, kMT, 0, stream>>>(book, w, status);
-      codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, w, status, (const MultiState*)(w + M.st));
+      codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, w, status, (const MultiState*)(w + M.st), stamps);
       e = hipGetLastError();
     }
   } else {
-    codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, w, status, nullptr);
+    codebook_kernel<1024><<<1, 1024, 0, stream>>>(hist, book, w, status, nullptr, stamps);
     e = hipGetLastError();
   }
   timer.after(stream);

@@ -48,6 +48,16 @@
 
 namespace hf {
 
+// Phase stamps of a traced build (hf_build_codebook_traced): lane 0 of
+// wave 0 stores the shader clock at the given index when `stamps` is set,
+// at points where it has just passed a workgroup barrier or where wave 0
+// alone carries on; untraced builds pass null and store nothing.
+#define HF_CB_STAMP(i)                                                              \
+  do {                                                                              \
+    if (stamps && threadIdx.x == 0) stamps[i] = __builtin_amdgcn_s_memtime();    \
+  } while (0)
+
+
 namespace {
 
 constexpr uint32_t kMaxLen = HF_MAX_CODELEN;
@@ -397,7 +407,8 @@ __device__ __forceinline__ void radix_sort_keys(uint64_t* key, uint64_t* tmp, ui
 // t.key[0, m) (m >= 2) and the depth of every internal node; returns the
 // array that holds the depths (one of t.dA, t.dB).
 template <typename IdT, int NT>
-__device__ __forceinline__ uint16_t* build_book_tree(const Tree<IdT>& t, Shared& sh, uint32_t m, uint32_t* status) {
+__device__ __forceinline__ uint16_t* build_book_tree(const Tree<IdT>& t, Shared& sh, uint32_t m, uint32_t* status,
+                                                     uint64_t* stamps = nullptr) {
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = tid / kWave;
   // ---- 3. GenerateCL rounds ------------------------------------------------
@@ -513,6 +524,7 @@ __device__ __forceinline__ uint16_t* build_book_tree(const Tree<IdT>& t, Shared&
   }
   }
 
+  HF_CB_STAMP(4);
   // ---- 4. depths of internal nodes ------------------------------------------
   // A node's parent is created in a later round, so with the round ends
   // recorded the depths follow round by round from the last (the root, at
@@ -566,7 +578,7 @@ __device__ __forceinline__ uint16_t* build_book_tree(const Tree<IdT>& t, Shared&
 template <typename IdT, int NT>
 __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const uint32_t* __restrict__ hist,
                                            uint32_t A, uint32_t m, uint32_t wmax, const hf_codebook& book,
-                                           uint32_t* status, uint32_t* lds_scratch) {
+                                           uint32_t* status, uint32_t* lds_scratch, uint64_t* stamps = nullptr) {
   constexpr int NW = NT / kWave;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
@@ -605,6 +617,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     return;
   }
 
+  HF_CB_STAMP(2);
   // ---- 2. sort leaves ascending by (count, u) --------------------------------
   if (m <= 512) {
     // rank sort: keys are distinct (u in the low bits); broadcast reads
@@ -626,8 +639,10 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   }
   __syncthreads();
 
-  uint16_t* dc = build_book_tree<IdT, NT>(t, sh, m, status);
+  HF_CB_STAMP(3);
+  uint16_t* dc = build_book_tree<IdT, NT>(t, sh, m, status, stamps);
 
+  HF_CB_STAMP(5);
   // ---- 5a. leaf lengths, counts per length, total bits ----------------------
   uint64_t bits = 0;
   uint32_t my_max = 0, my_min = 0xFFFFFFFFu;
@@ -675,6 +690,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
   }
   __syncthreads();
 
+  HF_CB_STAMP(6);
   // ---- 5b. First and Entry (wave 0; lane j holds length j + 1) ----------------
   if (wave == 0) {
     const uint32_t L = sh.lmax > kMaxLen ? kMaxLen : sh.lmax;
@@ -703,6 +719,7 @@ __device__ __forceinline__ void build_book(const Tree<IdT>& t, Shared& sh, const
     book.entry[l] = sh.entry[l];
   }
 
+  HF_CB_STAMP(7);
   // ---- 5c. rank within each length in symbol order -------------------------
   // Wave w takes a contiguous segment of compact indices.  In each 64-symbol
   // group the lanes sharing my length are the AND over the length's 7 bits
@@ -932,7 +949,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
 
 template <int NT, typename Lds>
 __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t narrow, const hf_codebook& book,
-                                                 uint32_t* status) {
+                                                 uint32_t* status, uint64_t* stamps = nullptr) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
@@ -958,6 +975,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
   for (uint32_t i = m + tid; i < kLeafSlots; i += NT) lw[i] = kInf32;
   for (uint32_t l = tid; l <= kMaxLen; l += NT) L.sh.cnt[l] = 0;
   __syncthreads();
+  HF_CB_STAMP(2);
 
   // ---- 2. rank sort: rank(e) = #{j : key_j < key_e} ---------------------------
   // The key is the count above the compact (symbol-order) index, so this is
@@ -999,6 +1017,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
     lu[r] = (uint16_t)tid;
   }
   __syncthreads();
+  HF_CB_STAMP(3);
   if (wave != 0) return;
 
   // ---- 3. GenerateCL rounds, one wave -----------------------------------------
@@ -1162,6 +1181,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
     wave_sync();  // parent links complete
   }
 
+  HF_CB_STAMP(4);
   // ---- 4. depths of internal nodes by pointer jumping ----------------------------
   // dn[k] = distance to the current jump target | target << 16, one word a node
   uint32_t* dn = (uint32_t*)(L.par + 2 * kSmallUsed);
@@ -1204,6 +1224,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
   }
   wave_sync();
 
+  HF_CB_STAMP(5);
   // ---- 5a. leaf lengths, counts per length, total bits ---------------------------
   // Total bits in two limbs per lane (this lane's sum of count x length is
   // below 2^40), each summed exactly by a DPP scan.
@@ -1226,6 +1247,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
   const uint64_t bits = ((uint64_t)readlane32(bhi, 63) << 24) + readlane32(blo, 63);
   wave_sync();
 
+  HF_CB_STAMP(6);
   // ---- 5b. First and Entry: lane j holds length j + 1 ---------------------------
   // The lengths present come from one ballot of the counts.  first[l] =
   // ceil((first[l+1] + cnt[l+1]) / 2) with first[Lc] = 0 unrolls to
@@ -1262,6 +1284,7 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
   }
   wave_sync();
 
+  HF_CB_STAMP(7);
   // ---- 5c. codewords: rank within each length in symbol order -------------------
   // The lanes of a 64-symbol chunk that share my length are the AND over
   // the length's 7 bits of that bit's ballot or its complement (unused
@@ -1310,7 +1333,7 @@ __device__ __forceinline__ void zero_unused(const uint32_t (&h)[4], uint32_t s0,
 // from those registers.
 template <int NT, typename Lds>
 __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist, const hf_codebook& book,
-                                               char* ws, uint32_t* status, Lds& L) {
+                                               char* ws, uint32_t* status, Lds& L, uint64_t* stamps = nullptr) {
   constexpr uint32_t C = Lds::kCap;
   constexpr int NW = NT / kWave;
   const uint32_t A = book.alphabet;
@@ -1339,6 +1362,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
       L.sh.wmax[wave] = mx;
     }
     __syncthreads();
+    HF_CB_STAMP(1);
     uint32_t pre = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -1362,7 +1386,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
           ++u;
         }
       }
-      build_book_small<NT>(L, m, narrow, book, status);
+      build_book_small<NT>(L, m, narrow, book, status, stamps);
       // Unused symbols get cl = cw = 0 from the waves that sit out the
       // rounds (wave 1 also covers wave 0's symbols); the used ones are
       // written by wave 0, so the two never meet.
@@ -1396,6 +1420,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
       L.sh.wmax[wave] = hm;
     }
     (void)block_exclusive_scan<NW>(c, L.sh.wtot, &m);  // (its barrier covers wsum and wmax)
+    HF_CB_STAMP(1);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       total += L.sh.wsum[w];
@@ -1404,7 +1429,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     __syncthreads();  // wtot is reused by the compaction
     if (m >= 2 && m <= kSmallUsed && total < 0xFFFFFFFFull) {
       compact<NT>(hist, A, L.key, L.usym, book, L.sh.wtot);  // 64-bit keys
-      build_book_small<NT>(L, m, 0, book, status);
+      build_book_small<NT>(L, m, 0, book, status, stamps);
       return;
     }
   }
@@ -1422,7 +1447,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = t.dA + C;
     t.nA = t.dB + C;
     t.nB = t.nA + C;
-    build_book<uint16_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw);
+    build_book<uint16_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw, stamps);
   } else {
     const GlobalLayout G = global_layout(A);
     Tree<uint32_t> t;
@@ -1437,7 +1462,7 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
     t.dB = (uint16_t*)(ws + G.dB);
     t.nA = (uint32_t*)(ws + G.nA);
     t.nB = (uint32_t*)(ws + G.nB);
-    build_book<uint32_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw);
+    build_book<uint32_t, NT>(t, L.sh, hist, A, m, wmax, book, status, (uint32_t*)L.iw, stamps);
   }
 }
 

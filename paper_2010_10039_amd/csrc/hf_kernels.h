@@ -80,8 +80,11 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
 // symbols are used.
 size_t codebook_workspace_bytes(uint32_t alphabet, uint32_t tree_cap = kCbLdsMaxUsed);
 
+// stamps: null, or 9 device words for the single-workgroup build's phase
+// clocks (hf_build_codebook_traced)
 hipError_t launch_codebook(const uint32_t* hist, const hf_codebook& book, void* ws, size_t ws_bytes,
-                           uint32_t* status, hipStream_t stream, const KernelTimer& timer);
+                           uint32_t* status, hipStream_t stream, const KernelTimer& timer,
+                           uint64_t* stamps = nullptr);
 
 // Encoder workspace: per-slab bit totals and last-32-bit records.
 size_t encode_workspace_bytes(uint32_t nslabs, uint32_t alphabet);

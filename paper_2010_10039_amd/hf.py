@@ -70,6 +70,8 @@ _lib.hf_histogram.argtypes = [_P, _U64, _U32, _U32, _P, _U32, _P, _P, _SZ, _P, _
 _lib.hf_histogram.restype = ctypes.c_int
 _lib.hf_build_codebook.argtypes = [_P, ctypes.POINTER(hf_codebook), _P, _SZ, _P, _P]
 _lib.hf_build_codebook.restype = ctypes.c_int
+_lib.hf_build_codebook_traced.argtypes = [_P, ctypes.POINTER(hf_codebook), _P, _SZ, _P, _P, _P]
+_lib.hf_build_codebook_traced.restype = ctypes.c_int
 _lib.hf_encode.argtypes = [_P, _U64, _U32, ctypes.POINTER(hf_codebook), _U32, _U32, _U32, _P, _P, _U64,
                            _P, _P, _SZ, _P, _P]
 _lib.hf_encode.restype = ctypes.c_int
@@ -259,6 +261,21 @@ def hf_build_codebook(hist: torch.Tensor, book: Codebook | None = None, ws: torc
     s = book.struct()
     _check(_lib.hf_build_codebook(_ptr(hist), ctypes.byref(s), _ptr(ws), 0 if ws is None else ws.numel(),
                                   _ptr(status), _stream()), "hf_build_codebook")
+    return book
+
+
+CODEBOOK_PHASES = ("histogram", "compaction", "sort", "rounds", "depths", "lengths", "first_entry", "codewords")
+
+
+def hf_build_codebook_traced(hist: torch.Tensor, book: Codebook, ws: torch.Tensor, status: torch.Tensor,
+                             stamps: torch.Tensor) -> Codebook:
+    """hf_build_codebook with the single-workgroup build's phase clocks
+    written to `stamps` (int64[9] on the device, zeroed by the caller)."""
+    if stamps.dtype != torch.int64 or stamps.numel() < 9:
+        raise ValueError("stamps must be an int64 tensor of at least 9 elements")
+    s = book.struct()
+    _check(_lib.hf_build_codebook_traced(_ptr(hist), ctypes.byref(s), _ptr(ws), ws.numel(), _ptr(status),
+                                         _ptr(stamps), _stream()), "hf_build_codebook_traced")
     return book
 
 

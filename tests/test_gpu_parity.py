@@ -283,6 +283,32 @@ def test_codebook_parity(name):
     assert_book_equal(book, ref)
 
 
+@pytest.mark.parametrize("name", ["m63_geom", "m231", "m3000_geom", "sparse8192", "m6000_geom_global", "zipf65536"])
+def test_codebook_traced_equals_untraced(name):
+    """The traced build is the same build: same book, and phase clocks that
+    rise through the phases of the single-workgroup build (none for books
+    built over the grid: alphabets above 8192 with more than 4096 used)."""
+    if name == "m231":
+        h = oracle.histogram(W.gaussian_codes(n=1 << 20, sigma=8.0, seed=3), 1024)
+    else:
+        h = HISTS[name]
+    ref = oracle.codebook(h)
+    hd = torch.from_numpy(h.view(np.int32)).cuda()
+    ws = hf.new_workspace(1, h.size)
+    status = hf.new_status()
+    book = hf.Codebook.empty(h.size, "cuda")
+    stamps = torch.zeros(9, dtype=torch.int64, device="cuda")
+    hf.hf_build_codebook_traced(hd, book, ws, status, stamps)
+    torch.cuda.synchronize()
+    assert hf.read_status(status) == 0
+    assert_book_equal(book, ref)
+    t = stamps.cpu().numpy()
+    if h.size > 8192 and ref.m > 4096:
+        assert np.all(t == 0)
+    else:
+        assert np.all(t > 0) and np.all(np.diff(t) >= 0), t
+
+
 def _random_small_books(count, seed):
     """Seeded books of 2..256 used symbols, scattered over alphabets up to
     1024 (one in five up to 65536), with counts that are tiny and tied, uniform, exponential, geometric,
