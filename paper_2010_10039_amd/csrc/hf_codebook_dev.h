@@ -818,6 +818,7 @@ constexpr uint32_t kSmallUsed = 256;
 constexpr uint32_t kInf32 = 0xFFFFFFFFu;
 
 constexpr uint32_t kLeafSlots = kSmallUsed + 2 * 64;  // sorted leaf weights, kInf32 past m
+constexpr uint32_t kSerialUsed = 40;  // up to this many used symbols the tree is built one node a step
 
 __device__ __forceinline__ uint32_t readlane32(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
@@ -947,6 +948,63 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
   return v;
 }
 
+// Books of at most kSerialUsed used symbols: the textbook two-queue build,
+// one node a step (the rounds cost about 1 K cycles each whatever their
+// size, and a book of a few dozen symbols can need as many rounds as
+// symbols).  Leaves, queued weights and parents sit one node a lane in
+// registers, so a step is four lane reads into scalar registers, a scalar
+// choice of the two lightest (leaf first on equal weight: the rounds' tie
+// rule, so the tree is the same) and lane selects; LDS is written once at
+// the end.  Run by one wave; not inlined, so that the rounds' code is
+// compiled as it is without it.
+__device__ __noinline__ void serial_tree(const uint32_t* lw, uint32_t* iw, uint16_t* parl, uint16_t* pari,
+                                         uint32_t m) {
+  const uint32_t lane = lane_id();
+  const uint32_t RW = lw[lane];        // leaf weights (kInf32 past m)
+  uint32_t IWr = kInf32;               // lane k: weight of internal node k
+  uint32_t PL = 0, PI = 0;             // lane e / k: parent of leaf e / internal node k
+  uint32_t lc = 0, ih = 0;
+  for (uint32_t k = 0; k + 1 < m; ++k) {
+    const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)RW, (int)lc);
+    const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)RW, (int)(lc + 1));
+    const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)IWr, (int)ih);      // kInf32 once ih = k
+    const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)IWr, (int)(ih + 1));
+    uint32_t w;
+    if (l0 <= i0) {  // first pick: leaf lc
+      PL = (lane == lc ? k : PL);
+      if (l1 <= i0) {  // second: leaf lc + 1
+        PL = (lane == (lc + 1) ? k : PL);
+        w = l0 + l1;
+        lc += 2;
+      } else {         // second: internal ih
+        PI = (lane == ih ? k : PI);
+        w = l0 + i0;
+        lc += 1;
+        ih += 1;
+      }
+    } else {         // first pick: internal ih
+      PI = (lane == ih ? k : PI);
+      if (l0 <= i1) {  // second: leaf lc
+        PL = (lane == lc ? k : PL);
+        w = i0 + l0;
+        lc += 1;
+        ih += 1;
+      } else {         // second: internal ih + 1
+        PI = (lane == (ih + 1) ? k : PI);
+        w = i0 + i1;
+        ih += 2;
+      }
+    }
+    IWr = (lane == k ? w : IWr);
+  }
+  if (lane < m) parl[lane] = (uint16_t)PL;
+  if (lane + 1 < m) {
+    pari[lane] = (uint16_t)PI;
+    iw[lane] = IWr;
+  }
+  wave_sync();
+}
+
 template <int NT, typename Lds>
 __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t narrow, const hf_codebook& book,
                                                  uint32_t* status, uint64_t* stamps = nullptr) {
@@ -1039,7 +1097,9 @@ __device__ __forceinline__ void build_book_small(Lds& L, uint32_t m, uint32_t na
   // merged through LDS by binary searches.  A round is one wave's dependent
   // chain, so the cursors are kept scalar (readfirstlane) and stores a lane
   // does not need go to a per-lane sink instead of behind a branch.
-  {
+  if (m <= kSerialUsed) {
+    serial_tree(lw, iw, parl, pari, m);
+  } else {
     constexpr uint64_t kPad64 = 0xFFFFFFFF0000FFFFull;  // above every real key
     constexpr uint32_t kPad32 = 0xFFFFFFFFu;
     constexpr uint32_t kKey32MaxW = (1u << 25) - 2;      // room for a 7-bit tag below kPad32
