@@ -122,6 +122,15 @@ constexpr uint32_t kMaxRegion = 96;                 // bits of one lane's region
 constexpr uint32_t kWinWords = 2 * kMaxRegion + 8;  // stream words staged per segment
 constexpr uint32_t kMapWords = 2 * kMaxRegion + 4;  // code-start bitmap words
 constexpr uint32_t kTabShort = 1u << 30;            // table entry: the symbol is in bits [0, 16)
+// Books of at most kPairAlphabet symbols (a symbol in 10 bits) use the pair
+// form of the table: an entry whose prefix fixes a first code of at most
+// kPeek bits has bit 31 set and holds that code's symbol (bits [0, 10)) and
+// length (bits [20, 24)), and, when the prefix's remaining bits also hold a
+// whole second code, its symbol (bits [10, 20)) and length (bits [24, 28),
+// else 0).  One lookup then decodes two codes where both fit the prefix
+// (two 6-bit codes on the Lorenzo stream: 57% of lookups).
+constexpr uint32_t kPairAlphabet = 1024;
+constexpr uint32_t kTabPair = 1u << 31;
 
 template <int SB>
 constexpr uint32_t tile_words() {
@@ -140,12 +149,12 @@ constexpr size_t decode_lds_bytes() {
 // Bits [16, 23): lo, the shortest code length among them, bits [23, 30): hi,
 // the longest.  When hi <= kPeek the prefix fixes the code (lo == hi): bit
 // 30 is set and bits [0, 16) hold its symbol, or the entry is 0 if no code
-// starts with p (an incomplete code).
+// starts with p (an incomplete code).  `pair`: the pair form above.
 __global__ __launch_bounds__(256) void decode_table_kernel(const uint64_t* __restrict__ first,
                                                            const uint32_t* __restrict__ entry,
                                                            const uint32_t* __restrict__ rev,
                                                            const uint64_t* __restrict__ info,
-                                                           uint32_t* __restrict__ tab) {
+                                                           uint32_t* __restrict__ tab, uint32_t pair) {
   const uint32_t p = blockIdx.x * 256u + threadIdx.x;
   if (p >= (1u << kPeek)) return;
   const uint32_t m = (uint32_t)info[0];
@@ -163,11 +172,29 @@ __global__ __launch_bounds__(256) void decode_table_kernel(const uint64_t* __res
     const uint64_t wmax = wmin | ((1ull << (64 - kPeek)) - 1);
     const uint32_t lo = len_of(wmax), hi = len_of(wmin);
     out = (lo << 16) | (hi << 23);
+    auto count_of = [&](uint32_t l) -> uint32_t { return (l < HF_MAX_CODELEN ? entry[l + 1] : m) - entry[l]; };
     if (hi <= kPeek) {
       const uint64_t v = p >> (kPeek - lo);
-      const uint32_t cnt = (lo < HF_MAX_CODELEN ? entry[lo + 1] : m) - entry[lo];
-      if (v >= first[lo] && v - first[lo] < cnt) out |= kTabShort | rev[entry[lo] + (uint32_t)(v - first[lo])];
-      else out = 0;
+      if (v >= first[lo] && v - first[lo] < count_of(lo)) {
+        const uint32_t sym = rev[entry[lo] + (uint32_t)(v - first[lo])];
+        if (!pair) {
+          out |= kTabShort | sym;
+        } else {
+          out = kTabPair | sym | lo << 20;
+          // a second code in the remaining R bits: its length is the smallest
+          // l <= R whose first l bits reach First[l] (the canonical rule)
+          const uint32_t R = kPeek - lo, q = p & ((1u << R) - 1u);
+          for (uint32_t l = 1; l <= R && l <= lmax; ++l) {
+            const uint64_t v2 = q >> (R - l);
+            if (v2 >= first[l]) {
+              if (v2 - first[l] < count_of(l)) out |= rev[entry[l] + (uint32_t)(v2 - first[l])] << 10 | l << 24;
+              break;
+            }
+          }
+        }
+      } else {
+        out = 0;
+      }
     }
   }
   tab[p] = out;
@@ -268,7 +295,7 @@ __device__ __forceinline__ void tile_copy_out(const uint32_t* tile, uint32_t h, 
   }
 }
 
-template <int SB>
+template <int SB, bool PAIR>
 __global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void decode_kernel(DecArgs a) {
   extern __shared__ __align__(16) uint32_t dlds[];
   __shared__ DecShared ds;
@@ -339,10 +366,22 @@ __global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
       uint32_t s = g, p = g, c = 0;
       while (p < rend) {
         const uint64_t W = dec_window(win, p);
-        const uint32_t len = dec_len(tab[W >> (64 - kPeek)], W, ds.lj);
+        const uint32_t t = tab[W >> (64 - kPeek)];
         atomicOr(&map[p >> 5], 1u << (p & 31));
-        p += len ? len : 1u;
         ++c;
+        if (PAIR && (t & kTabPair)) {
+          const uint32_t q = p + ((t >> 20) & 15u), l2 = (t >> 24) & 15u;
+          if (l2 && q < rend) {  // the second code starts in this region too
+            atomicOr(&map[q >> 5], 1u << (q & 31));
+            ++c;
+            p = q + l2;
+          } else {
+            p = q;
+          }
+        } else {
+          const uint32_t len = dec_len(t, W, ds.lj);
+          p += len ? len : 1u;
+        }
       }
       const uint32_t eA = p;
       uint32_t e = p;
@@ -365,9 +404,20 @@ __global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
               break;
             }
             const uint64_t W = dec_window(win, p);
-            const uint32_t len = dec_len(tab[W >> (64 - kPeek)], W, ds.lj);
-            p += len ? len : 1u;
+            const uint32_t t = tab[W >> (64 - kPeek)];
             ++cn;
+            if (PAIR && (t & kTabPair)) {
+              const uint32_t q = p + ((t >> 20) & 15u), l2 = (t >> 24) & 15u;
+              if (l2 && q < rend && !((map[q >> 5] >> (q & 31)) & 1u)) {  // (a mark at q ends the walk there)
+                ++cn;
+                p = q + l2;
+              } else {
+                p = q;
+              }
+            } else {
+              const uint32_t len = dec_len(t, W, ds.lj);
+              p += len ? len : 1u;
+            }
           }
           if (met) {
             cn += count_marks(map, p, rend);
@@ -397,6 +447,18 @@ __global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         while (!lbad && td < c && o + td < rb + kTile) {
           const uint64_t W = dec_window(win, p);
           const uint32_t t = tab[W >> (64 - kPeek)];
+          if (PAIR && (t & kTabPair)) {
+            tile_put<SB>(tile, h + o + td - rb, t & 1023u);
+            p += (t >> 20) & 15u;
+            ++td;
+            const uint32_t l2 = (t >> 24) & 15u;
+            if (l2 && td < c && o + td < rb + kTile) {
+              tile_put<SB>(tile, h + o + td - rb, (t >> 10) & 1023u);
+              p += l2;
+              ++td;
+            }
+            continue;
+          }
           const uint32_t len = dec_len(t, W, ds.lj);
           uint32_t sym = t & 0xFFFFu;
           if (!(t & kTabShort)) {
@@ -446,17 +508,19 @@ hipError_t launch_decode(const uint32_t* words, const uint64_t* offsets, uint64_
     return hipSuccess;
   }
   uint32_t* tab = (uint32_t*)ws;
-  decode_table_kernel<<<(1u << kPeek) / 256, 256, 0, stream>>>(book.first, book.entry, book.rev, book.info, tab);
+  const bool pair = book.alphabet <= kPairAlphabet;
+  decode_table_kernel<<<(1u << kPeek) / 256, 256, 0, stream>>>(book.first, book.entry, book.rev, book.info, tab,
+                                                                pair ? 1u : 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   static std::once_flag once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute((const void*)decode_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)decode_lds_bytes<1>());
-    if (attr_err == hipSuccess)
-      attr_err = hipFuncSetAttribute((const void*)decode_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)decode_lds_bytes<2>());
+    const void* fns[4] = {(const void*)decode_kernel<1, false>, (const void*)decode_kernel<1, true>,
+                          (const void*)decode_kernel<2, false>, (const void*)decode_kernel<2, true>};
+    for (int i = 0; i < 4 && attr_err == hipSuccess; ++i)
+      attr_err = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(i < 2 ? decode_lds_bytes<1>() : decode_lds_bytes<2>()));
   });
   if (attr_err != hipSuccess) return attr_err;
   const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
@@ -465,8 +529,13 @@ hipError_t launch_decode(const uint32_t* words, const uint64_t* offsets, uint64_
   const uint32_t grid = (uint32_t)min(want, (uint64_t)max(1, num_cus) * 2);
   DecArgs a{words, offsets, n, chunk_log2, nchunks, tab, book.first, book.entry, book.rev, book.info, out, status};
   timer.before(stream);
-  if (sym_bytes == 1) decode_kernel<1><<<grid, kDWG, decode_lds_bytes<1>(), stream>>>(a);
-  else decode_kernel<2><<<grid, kDWG, decode_lds_bytes<2>(), stream>>>(a);
+  if (sym_bytes == 1) {
+    if (pair) decode_kernel<1, true><<<grid, kDWG, decode_lds_bytes<1>(), stream>>>(a);
+    else decode_kernel<1, false><<<grid, kDWG, decode_lds_bytes<1>(), stream>>>(a);
+  } else {
+    if (pair) decode_kernel<2, true><<<grid, kDWG, decode_lds_bytes<2>(), stream>>>(a);
+    else decode_kernel<2, false><<<grid, kDWG, decode_lds_bytes<2>(), stream>>>(a);
+  }
   e = hipGetLastError();
   timer.after(stream);
   return e;
