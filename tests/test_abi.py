@@ -221,3 +221,32 @@ def test_binding_refuses_host_tensors():
         hf._dptr(x)
     with pytest.raises(ValueError, match="GPU tensors only"):
         hf.hf_histogram(x, 1024, status=torch.zeros(1, dtype=torch.int32))
+
+
+def test_codebook_argument_checks(lib):
+    """hf_build_codebook and its traced variant reject bad arguments before
+    any device work; alphabets above 4096 need the workspace, and above 8192
+    the larger one of the grid-wide steps."""
+    P, SZ = ctypes.c_void_p, ctypes.c_size_t
+    for f in (lib.hf_build_codebook, lib.hf_build_codebook_traced):
+        traced = f is lib.hf_build_codebook_traced
+        f.argtypes = [P, ctypes.POINTER(_Book), P, SZ, P] + ([P] if traced else []) + [P]
+
+        def call(hist, book, ws, ws_bytes, status, stamps=P(0x9000)):
+            args = [hist, ctypes.byref(book), ws, ws_bytes, status] + ([stamps] if traced else []) + [None]
+            return f(*args)
+
+        d, ws = P(0x1000), P(0x100000)
+        assert call(None, _Book(1024, *([0x2000] * 6)), None, 0, d) == 1       # no histogram
+        assert call(d, _Book(0, *([0x2000] * 6)), None, 0, d) == 1             # alphabet 0
+        assert call(d, _Book(65537, *([0x2000] * 6)), None, 0, d) == 1         # alphabet > 65536
+        assert call(d, _Book(1024, *([0x2000] * 6)), None, 0, None) == 1       # no status word
+        assert call(d, _Book(8192, *([0x2000] * 6)), None, 0, d) == 2          # tree in the workspace
+        lib.hf_workspace_bytes.restype = SZ
+        lib.hf_workspace_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        small, big = lib.hf_workspace_bytes(1, 8192, 4096), lib.hf_workspace_bytes(1, 65536, 4096)
+        assert big > small > 0
+        assert call(d, _Book(65536, *([0x2000] * 6)), ws, big - 256, d) == 2  # too small for the grid-wide steps
+        assert call(d, _Book(65536, *([0x2000] * 6)), P(0x100004), big, d) == 2  # misaligned
+        if traced:
+            assert call(d, _Book(1024, *([0x2000] * 6)), None, 0, d, stamps=None) == 1  # no stamp array

@@ -262,6 +262,9 @@ def _hist_cases():
     h = np.zeros(65536, np.uint32)
     h[rng.choice(65536, size=5000, replace=False)] = rng.choice(np.array([1, 2, 2, 3, 7], np.uint32), size=5000)
     cases["multi_ties_m5000_a65536"] = h
+    cases["multi_empty_a16384"] = np.zeros(16384, np.uint32)
+    h = np.zeros(65536, np.uint32); h[40000] = 7; cases["multi_one_a65536"] = h
+    h = np.zeros(65536, np.uint32); h[3] = 1; h[65535] = 2; cases["multi_two_a65536"] = h
     # the sum of counts just below / at 2^32 - 1 (register path / general path)
     h = np.zeros(1024, np.uint32); h[:200] = 1; h[500] = 0xFFFFFFFE - 200 - 7; h[501:508] = 1
     assert int(h.sum(dtype=np.uint64)) == 0xFFFFFFFE
