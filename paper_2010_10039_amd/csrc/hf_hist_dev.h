@@ -109,6 +109,56 @@ __device__ __forceinline__ void hist_range(uint32_t* subr, const void* __restric
   }
 }
 
+// Interleaved replicas (bin b of replica r at word b R + r, lane l using
+// replica l mod R) over the whole alphabet plus the trash bin A: lanes of
+// different replicas that hit one bin use R consecutive banks, and
+// neighbouring bins are R banks apart (peaked data sits on neighbouring
+// bins).  Loads as in hist_range.
+__device__ __forceinline__ void hist_count_il(uint32_t* subr, uint32_t s, uint32_t A, uint32_t R) {
+  atomicAdd(&subr[min(s, A) * R], 1u);
+}
+
+template <int SB>
+__device__ __forceinline__ void hist_count_vec_il(uint32_t* subr, uint4 v, uint32_t A, uint32_t R) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (SB == 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) hist_count_il(subr, (w[k] >> (8 * j)) & 0xFFu, A, R);
+    } else {
+      hist_count_il(subr, w[k] & 0xFFFFu, A, R);
+      hist_count_il(subr, w[k] >> 16, A, R);
+    }
+  }
+}
+
+template <int SB>
+__device__ __forceinline__ void hist_range_il(uint32_t* sub, uint32_t R, const void* __restrict__ sym,
+                                              uint64_t s_lo, uint64_t s_hi, uint32_t A) {
+  constexpr uint32_t kPerVec = 16 / SB;
+  const uint32_t tid = threadIdx.x;
+  uint32_t* const subr = sub + (tid & (R - 1));
+  const uintptr_t addr = (uintptr_t)sym + s_lo * SB;
+  uint64_t head = ((16 - (addr & 15)) & 15) / SB;
+  if (head > s_hi - s_lo) head = s_hi - s_lo;
+  const uint64_t nvec = (s_hi - s_lo - head) / kPerVec;
+  const uint4* body = (const uint4*)((const char*)sym + (s_lo + head) * SB);
+  uint64_t v = tid;
+  constexpr int kUnroll = 4;
+  for (; v + (kUnroll - 1) * (uint64_t)blockDim.x < nvec; v += kUnroll * (uint64_t)blockDim.x) {
+    uint4 q[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) q[u] = body[v + u * (uint64_t)blockDim.x];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) hist_count_vec_il<SB>(subr, q[u], A, R);
+  }
+  for (; v < nvec; v += blockDim.x) hist_count_vec_il<SB>(subr, body[v], A, R);
+  for (uint64_t i = tid; i < head; i += blockDim.x) hist_count_il(subr, sym_load<SB>(sym, s_lo + i), A, R);
+  for (uint64_t i = s_lo + head + nvec * kPerVec + tid; i < s_hi; i += blockDim.x)
+    hist_count_il(subr, sym_load<SB>(sym, i), A, R);
+}
+
 // Words of LDS a window needs: R replicas, hist_stride words apart.
 __host__ __device__ inline uint32_t hist_window_words(uint32_t W, uint32_t A, uint32_t R) {
   return hist_stride(W, A) * R;
@@ -123,22 +173,21 @@ __device__ __forceinline__ void batch_hist_item(const BatchStream& bs, uint32_t 
   uint32_t R = 1;
   while (R < 16 && Wp * R * 2 <= lds_words) R *= 2;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < Wp * R; i += blockDim.x) sub[i] = 0;
+  for (uint32_t i = tid; i < (A + 1) * R; i += blockDim.x) sub[i] = 0;
   __syncthreads();
   const uint64_t s_lo = slab_begin(g, bs.nblocks, bs.nslabs, bs.n);
   const uint64_t s_hi = slab_begin(g + 1, bs.nblocks, bs.nslabs, bs.n);
   bool bad = false;
-  uint32_t* const subr = sub + (tid & (R - 1)) * Wp;
-  if (bs.sym_bytes == 1) hist_range<1, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
-  else hist_range<2, true>(subr, bs.sym, s_lo, s_hi, 0, A, A, bad);
+  if (bs.sym_bytes == 1) hist_range_il<1>(sub, R, bs.sym, s_lo, s_hi, A);
+  else hist_range_il<2>(sub, R, bs.sym, s_lo, s_hi, A);
   __syncthreads();
   uint32_t* row = bs.part + (uint64_t)g * A;
   for (uint32_t b = tid; b < A; b += blockDim.x) {
     uint32_t c = 0;
-    for (uint32_t r = 0; r < R; ++r) c += sub[r * Wp + b];
+    for (uint32_t r = 0; r < R; ++r) c += sub[b * R + r];
     row[b] = c;
   }
-  if (tid < R && sub[tid * Wp + A]) bad = true;
+  if (tid < R && sub[A * R + tid]) bad = true;
   if (bad) raise_status(bs.status, HF_ERR_SYMBOL);
 }
 
