@@ -192,8 +192,13 @@ hf_status hf_encode_paper(const void* d_sym, uint64_t n, uint32_t sym_bytes, con
  * rank, which is exactly the code a heap-based Huffman construction gives
  * under that order; codewords are canonical as described above.  One
  * workgroup builds the book; the tree lives in LDS when at most 4096
- * symbols are used, else in the workspace.  Raises HF_ERR_CODELEN if a code
- * would exceed 64 bits.
+ * symbols are used, else in the workspace.  For alphabets above 8192 with
+ * more than 4096 used symbols the sort, the code lengths and the codewords
+ * run over up to 64 workgroups (the rounds stay in one); the workspace
+ * (hf_workspace_bytes) then also holds their buffers.  Enqueues up to five
+ * kernels, none of which waits for the host.  Raises HF_ERR_CODELEN if a
+ * code would exceed 64 bits, HF_ERR_INTERNAL if a bounded wait between the
+ * grid-wide steps' workgroups ran out.
  */
 hf_status hf_build_codebook(const uint32_t* d_hist, const hf_codebook* book, void* d_ws,
                             size_t ws_bytes, uint32_t* d_status, void* stream);
