@@ -954,12 +954,16 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
 // symbols).  Leaves, queued weights and parents sit one node a lane in
 // registers, so a step is four lane reads into scalar registers, a scalar
 // choice of the two lightest (leaf first on equal weight: the rounds' tie
-// rule, so the tree is the same) and lane selects; LDS is written once at
-// the end.  Run by one wave; not inlined, so that the rounds' code is
+// rule, so the tree is the same) and lane selects, without branches; LDS is
+// written once at the end.  Run by one wave; not inlined, so that the rounds' code is
 // compiled as it is without it.
 __device__ __noinline__ void serial_tree(const uint32_t* lw, uint32_t* iw, uint16_t* parl, uint16_t* pari,
-                                         uint32_t m) {
+                                         uint32_t m_arg) {
   const uint32_t lane = lane_id();
+  // m is wave-uniform; read it into a scalar register so that the walk's
+  // loop, its cursors and its choices stay scalar (arguments of a call come
+  // in vector registers)
+  const uint32_t m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m_arg);
   const uint32_t RW = lw[lane];        // leaf weights (kInf32 past m)
   uint32_t IWr = kInf32;               // lane k: weight of internal node k
   uint32_t PL = 0, PI = 0;             // lane e / k: parent of leaf e / internal node k
@@ -969,33 +973,19 @@ __device__ __noinline__ void serial_tree(const uint32_t* lw, uint32_t* iw, uint1
     const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)RW, (int)(lc + 1));
     const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)IWr, (int)ih);      // kInf32 once ih = k
     const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)IWr, (int)(ih + 1));
-    uint32_t w;
-    if (l0 <= i0) {  // first pick: leaf lc
-      PL = (lane == lc ? k : PL);
-      if (l1 <= i0) {  // second: leaf lc + 1
-        PL = (lane == (lc + 1) ? k : PL);
-        w = l0 + l1;
-        lc += 2;
-      } else {         // second: internal ih
-        PI = (lane == ih ? k : PI);
-        w = l0 + i0;
-        lc += 1;
-        ih += 1;
-      }
-    } else {         // first pick: internal ih
-      PI = (lane == ih ? k : PI);
-      if (l0 <= i1) {  // second: leaf lc
-        PL = (lane == lc ? k : PL);
-        w = i0 + l0;
-        lc += 1;
-        ih += 1;
-      } else {         // second: internal ih + 1
-        PI = (lane == (ih + 1) ? k : PI);
-        w = i0 + i1;
-        ih += 2;
-      }
-    }
+    // branch-free: the two picks, then the parents they get and the cursors
+    const bool p1 = l0 <= i0;                   // first pick is leaf lc, else internal ih
+    const uint32_t nl = p1 ? l1 : l0, ni = p1 ? i0 : i1;
+    const bool p2 = nl <= ni;                   // second pick is a leaf, else an internal node
+    const uint32_t w = (p1 ? l0 : i0) + (p2 ? nl : ni);
+    const uint32_t l2 = lc + (p1 ? 1u : 0u), i2 = ih + (p1 ? 0u : 1u);  // where the second pick sits
+    const bool leaf_here = (p1 && lane == lc) || (p2 && lane == l2);
+    const bool int_here = (!p1 && lane == ih) || (!p2 && lane == i2);
+    PL = leaf_here ? k : PL;
+    PI = int_here ? k : PI;
     IWr = (lane == k ? w : IWr);
+    lc = l2 + (p2 ? 1u : 0u);
+    ih = i2 + (p2 ? 0u : 1u);
   }
   if (lane < m) parl[lane] = (uint16_t)PL;
   if (lane + 1 < m) {
