@@ -526,7 +526,7 @@ __global__ __launch_bounds__(NT) void codebook_kernel(const uint32_t* __restrict
   if (multi && multi->m > kCbLdsMaxUsed) return;  // built by the grid-wide steps
   __shared__ CbLds lds;
   HF_CB_STAMP(0);
-  codebook_block<NT>(hist, book, ws, status, lds, stamps);
+  codebook_block<NT>(hist, book, ws, status, lds, stamps, multi != nullptr);  // (sort_count zeroed the unused)
   if (stamps) {
     __syncthreads();
     HF_CB_STAMP(8);

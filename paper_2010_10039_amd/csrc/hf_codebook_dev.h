@@ -260,7 +260,9 @@ __device__ __forceinline__ void rounds_one_wave(const Tree<IdT>& t, uint32_t m, 
 
 // Compaction in symbol order, NT symbols at a time (coalesced reads): used
 // symbol s gets compact index u (its rank among used symbols), key[u] =
-// count << 16 | u and usym[u] = s; unused symbols get cl = cw = 0.
+// count << 16 | u and usym[u] = s.  (Unused symbols' cl = cw = 0 are
+// written by the histogram pass of codebook_block, with lane-contiguous
+// stores, or before it by the grid-wide count of a large alphabet.)
 template <int NT, typename IdT>
 __device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint32_t A, uint64_t* key, IdT* usym,
                                         const hf_codebook& book, uint32_t* wtot) {
@@ -283,9 +285,6 @@ __device__ __forceinline__ void compact(const uint32_t* __restrict__ hist, uint3
         key[u] = ((uint64_t)h[v] << 16) | u;
         usym[u] = (IdT)(s + v);
         ++u;
-      } else if (s + v < A) {
-        book.cl[s + v] = 0;
-        book.cw[s + v] = 0;
       }
     }
     run += tot;
@@ -1383,7 +1382,8 @@ __device__ __forceinline__ void zero_unused(const uint32_t (&h)[4], uint32_t s0,
 // from those registers.
 template <int NT, typename Lds>
 __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist, const hf_codebook& book,
-                                               char* ws, uint32_t* status, Lds& L, uint64_t* stamps = nullptr) {
+                                               char* ws, uint32_t* status, Lds& L, uint64_t* stamps = nullptr,
+                                               bool zeroed = false) {
   constexpr uint32_t C = Lds::kCap;
   constexpr int NW = NT / kWave;
   const uint32_t A = book.alphabet;
@@ -1452,16 +1452,31 @@ __device__ __forceinline__ void codebook_block(const uint32_t* __restrict__ hist
       }
       return;
     }
+    zero_unused(h, 4 * tid, A, book);
     __syncthreads();  // wtot is reused by the compaction
   } else {
     uint32_t c = 0, hm = 0;
     uint64_t wsum = 0;
+    if (zeroed) {  // two loops: a possible store between the loads would keep them from being batched
 #pragma unroll 8
-    for (uint32_t s = tid; s < A; s += NT) {
-      const uint32_t h = hist[s];
-      c += (h != 0);
-      wsum += h;
-      hm = max(hm, h);
+      for (uint32_t s = tid; s < A; s += NT) {
+        const uint32_t h = hist[s];
+        c += (h != 0);
+        wsum += h;
+        hm = max(hm, h);
+      }
+    } else {
+#pragma unroll 8
+      for (uint32_t s = tid; s < A; s += NT) {
+        const uint32_t h = hist[s];
+        c += (h != 0);
+        wsum += h;
+        hm = max(hm, h);
+        if (!h) {  // unused: no code (lane-contiguous stores)
+          book.cl[s] = 0;
+          book.cw[s] = 0;
+        }
+      }
     }
     wsum = wave_sum_u64(wsum);
     hm = wave_max_u32(hm);
