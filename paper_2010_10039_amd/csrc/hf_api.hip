@@ -281,7 +281,7 @@ hf_status hf_encode_paper(const void* d_sym, uint64_t n, uint32_t sym_bytes, con
   return launch_result(hf::launch_encode_paper(d_sym, n, sym_bytes, *book, chunk_log2, reduce_log2, d_out,
                                                out_capacity_words, d_chunk_word_offsets, d_break_groups,
                                                d_break_syms, break_capacity, d_nbreak, d_ws, d_status,
-                                               (hipStream_t)stream, timer));
+                                               (uint32_t)num_cus(), (hipStream_t)stream, timer));
 }
 
 size_t hf_decode_workspace_bytes(void) { return hf::decode_workspace_bytes(); }

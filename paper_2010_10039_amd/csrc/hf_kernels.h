@@ -74,7 +74,7 @@ size_t paper_workspace_bytes(uint64_t n, uint32_t chunk_log2);
 hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
                                uint32_t M, uint32_t r, uint32_t* out, uint64_t cap_words, uint64_t* offsets,
                                uint64_t* brk_groups, void* brk_syms, uint64_t brk_cap, uint64_t* nbreak, void* ws,
-                               uint32_t* status, hipStream_t stream, const KernelTimer& timer);
+                               uint32_t* status, uint32_t cus, hipStream_t stream, const KernelTimer& timer);
 
 // Workspace bytes the codebook kernel needs when more than kCbLdsMaxUsed
 // symbols are used.

@@ -10,9 +10,10 @@
 // a whole 32-bit word; chunks follow one another word-aligned.
 //
 // Three launches: per-chunk bit and breaking counts; one workgroup scanning
-// them into word and side-channel offsets (and checking capacities); per
-// chunk, a workgroup scan of its groups' lengths, the words ORed into an LDS
-// image of the chunk, and whole words copied out.
+// them into word and side-channel offsets (and checking capacities); a
+// workgroup scan of the groups' lengths, the words ORed into an LDS image of
+// the chunk, and whole words copied out.  A workgroup takes a tile of 4096
+// symbols (8192 at r = 5), one or more whole chunks.
 #include <algorithm>
 
 #include "hf_device.h"
@@ -24,36 +25,88 @@ namespace {
 
 constexpr int kPfThreads = 256;
 constexpr int kPfWaves = kPfThreads / kWave;
-constexpr int kPfMaxPer = 8;  // groups per thread: 2^(12 - 1) groups / 256 threads
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;    // chunks per scan thread
+constexpr int kPfMaxChunks = 32;  // chunks per tile: 2^(13 - 8)
+constexpr uint32_t kPfBlocksPerCu = 8;
 
-// Merged word of the group [g0, g1): right-aligned code bits, valid while
-// len <= 32; `bad` is set by a symbol outside the alphabet or without a code.
-template <int SB>
-__device__ __forceinline__ void group_word(const void* sym, uint64_t g0, uint64_t g1, const uint8_t* cl,
-                                           const uint64_t* cw, uint32_t A, uint32_t& word, uint32_t& len,
+// A workgroup takes a tile of 2^TL symbols, TL = max(12, 8 + R): every
+// thread holds 16 (or, at R = 5, 32) consecutive symbols, pf_per groups,
+// all in one chunk, and the tile holds 2^(TL - M) whole chunks.
+template <int R>
+constexpr uint32_t pf_tile_log2() {
+  return R < 5 ? 12u : 13u;
+}
+template <int R>
+constexpr int pf_per() {
+  return 1 << (pf_tile_log2<R>() - 8 - R);
+}
+
+// Merged words of this thread's NS = PER G symbols starting at `first`, of
+// which the first `rem` are its own (FULL: all of them): right-aligned code
+// bits, valid while len <= 32; `bad` is set by a symbol outside the alphabet
+// or without a code.  All symbol loads and table lookups are issued before
+// any merge, so they are in flight together; a partial thread clamps its
+// loads into the stream and masks what lies past `rem`.  A code that enters
+// a word has at most 32 bits, so only the low half of its 64-bit codeword is
+// read: cw32[2 s] from the book, or tab[s] from the workgroup's LDS copy
+// (TAB); and while a word fits, its bits so far and the next code fit in 32
+// bits (a 32-bit code comes only into an empty word).
+template <int SB, int R, int PER, bool TAB, bool FULL>
+__device__ __forceinline__ void words_body(const void* sym, uint64_t n, uint64_t first, uint32_t rem,
+                                           const uint8_t* cl, const uint32_t* cw32, uint32_t A,
+                                           uint32_t (&word)[PER], uint32_t (&len)[PER], uint32_t (&s)[PER << R],
                                            bool& bad) {
-  uint64_t acc = 0;
-  uint32_t L = 0;
-  for (uint64_t i = g0; i < g1; ++i) {
-    const uint32_t s = sym_at<SB>(sym, i);
-    const uint32_t l = s < A ? cl[s] : 0u;
-    bad |= l == 0;
-    if (L + l <= 32) acc = (acc << l) | cw[s < A ? s : 0];
-    L += l;
+  constexpr int G = 1 << R, NS = PER * G;
+  uint32_t l[NS], c[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s[i] = FULL ? sym_at<SB>(sym, first + i) : sym_at<SB>(sym, std::min<uint64_t>(first + i, n - 1));
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const uint32_t t = s[i] < A ? s[i] : 0u;
+    l[i] = s[i] < A ? (uint32_t)cl[t] : 0u;
+    c[i] = cw32[TAB ? t : 2 * t];
   }
-  word = (uint32_t)acc;
-  len = L;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    uint32_t acc = 0, L = 0;
+#pragma unroll
+    for (int i = j * G; i < (j + 1) * G; ++i) {
+      const bool in = FULL || (uint32_t)i < rem;
+      const uint32_t li = in ? l[i] : 0u;
+      bad |= in && li == 0;
+      acc = in && L + li <= 32 ? (acc << (li & 31)) | c[i] : acc;
+      L += li;
+    }
+    word[j] = acc;
+    len[j] = L;
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s[i] = FULL || (uint32_t)i < rem ? s[i] : 0u;
+}
+
+// This thread's groups [ga, gb) of the chunk whose symbols end at hi; the
+// symbols are returned too (0 past the thread's own).
+template <int SB, int R, int PER, bool TAB>
+__device__ __forceinline__ void thread_words(const void* sym, uint64_t n, uint64_t lo, uint64_t hi, uint32_t ga,
+                                             uint32_t gb, const uint8_t* cl, const uint32_t* cw32, uint32_t A,
+                                             uint32_t (&word)[PER], uint32_t (&len)[PER], uint32_t (&syms)[PER << R],
+                                             bool& bad) {
+  constexpr uint32_t NS = PER << R;
+  const uint64_t first = lo + ((uint64_t)ga << R);
+  const uint64_t end = std::min<uint64_t>(hi, lo + ((uint64_t)gb << R));
+  const uint32_t rem = end > first ? (uint32_t)std::min<uint64_t>(end - first, NS) : 0u;
+  if (rem == NS) words_body<SB, R, PER, TAB, true>(sym, n, first, rem, cl, cw32, A, word, len, syms, bad);
+  else words_body<SB, R, PER, TAB, false>(sym, n, first, rem, cl, cw32, A, word, len, syms, bad);
 }
 
 struct PfArgs {
   const void* sym;
   uint64_t n;
   const uint8_t* cl;
-  const uint64_t* cw;
+  const uint32_t* cw32;  // the book's 64-bit codewords, read as 32-bit halves
   uint32_t A;
   uint32_t M;
-  uint32_t r;
   uint64_t nch;
   uint32_t* chunk_bits;  // ws
   uint32_t* chunk_brk;   // ws
@@ -68,62 +121,148 @@ struct PfArgs {
   uint32_t* status;
 };
 
-template <int SB>
-__global__ __launch_bounds__(kPfThreads) void pf_count_kernel(PfArgs a) {
-  __shared__ uint32_t sbits, sbrk;
-  if (threadIdx.x == 0) sbits = sbrk = 0;
+// This thread's chunk in the tile (c-th of the tile, k in all, nch or more
+// for none) and its groups [ga, gb) of that chunk.
+template <int R>
+__device__ __forceinline__ void pf_thread_groups(const PfArgs& a, uint64_t tile, uint32_t& c, uint64_t& k,
+                                                 uint64_t& lo, uint64_t& hi, uint32_t& ga, uint32_t& gb) {
+  constexpr uint32_t TL = pf_tile_log2<R>();
+  const uint32_t tid = threadIdx.x, tpc = a.M + 8 - TL;  // log2 threads per chunk
+  c = tid >> tpc;
+  k = (tile << (TL - a.M)) + c;
+  ga = gb = 0;
+  lo = hi = 0;
+  if (k >= a.nch) return;
+  lo = k << a.M;
+  hi = std::min<uint64_t>(a.n, lo + (1ull << a.M));
+  const uint32_t ng = (uint32_t)((hi - lo + (1u << R) - 1) >> R);
+  ga = std::min(ng, (tid & ((1u << tpc) - 1)) * (uint32_t)pf_per<R>());
+  gb = std::min(ng, ga + (uint32_t)pf_per<R>());
+}
+
+// The workgroup's copy of the book when the alphabet has at most
+// kPfTabAlphabet symbols: the codewords' low halves, then the lengths.
+constexpr uint32_t kPfTabAlphabet = 4096;
+extern __shared__ uint32_t pf_tab[];
+
+__host__ __device__ inline uint32_t pf_tab_bytes(uint32_t A) { return (A * 5 + 3) & ~3u; }
+
+template <bool TAB>
+__device__ __forceinline__ void pf_stage_book(const PfArgs& a, const uint8_t*& cl, const uint32_t*& cw) {
+  cl = a.cl;
+  cw = a.cw32;
+  if (!TAB) return;
+  uint8_t* tcl = (uint8_t*)(pf_tab + a.A);
+#pragma unroll 4
+  for (uint32_t i = threadIdx.x; i < a.A; i += kPfThreads) {
+    pf_tab[i] = a.cw32[2 * i];
+    tcl[i] = a.cl[i];
+  }
   __syncthreads();
-  const uint64_t k = blockIdx.x;
-  const uint64_t lo = k << a.M;
-  const uint64_t hi = std::min<uint64_t>(a.n, lo + (1ull << a.M));
-  const uint32_t G = 1u << a.r;
-  const uint32_t ng = (uint32_t)((hi - lo + G - 1) >> a.r);
-  uint32_t bits = 0, brk = 0;
+  cl = tcl;
+  cw = pf_tab;
+}
+
+// Each workgroup stages the book once and loops over tiles.
+template <int SB, int R, bool TAB>
+__global__ __launch_bounds__(kPfThreads) void pf_count_kernel(PfArgs a, uint64_t ntiles) {
+  constexpr uint32_t TL = pf_tile_log2<R>();
+  constexpr int PER = pf_per<R>();
+  __shared__ uint32_t sacc[kPfMaxChunks];  // per chunk: breaking groups << 20 | bits
+  const uint8_t* cl;
+  const uint32_t* cw;
+  pf_stage_book<TAB>(a, cl, cw);
+  const uint32_t cpw = 1u << (TL - a.M), tid = threadIdx.x;
   bool bad = false;
-  for (uint32_t g = threadIdx.x; g < ng; g += kPfThreads) {
-    const uint64_t g0 = lo + ((uint64_t)g << a.r);
-    uint32_t w, L;
-    group_word<SB>(a.sym, g0, std::min<uint64_t>(hi, g0 + G), a.cl, a.cw, a.A, w, L, bad);
-    if (L > 32) ++brk;
-    else bits += L;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (tid < cpw) sacc[tid] = 0;
+    __syncthreads();
+    uint32_t c, ga, gb;
+    uint64_t k, lo, hi;
+    pf_thread_groups<R>(a, tile, c, k, lo, hi, ga, gb);
+    uint32_t word[PER], len[PER], syms[PER << R];
+    thread_words<SB, R, PER, TAB>(a.sym, a.n, lo, hi, ga, gb, cl, cw, a.A, word, len, syms, bad);
+    uint32_t bits = 0, brk = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      brk += len[j] > 32;
+      bits += len[j] > 32 ? 0u : len[j];
+    }
+    // a chunk's bits <= 2^16 and breaking groups <= 2^11: one packed sum over
+    // the lanes of the chunk (a power of two up to the whole wave)
+    uint32_t v = (brk << 20) | bits;
+    const uint32_t width = std::min(1u << (a.M + 8 - TL), (uint32_t)kWave);
+    for (uint32_t o = 1; o < width; o <<= 1) v += __shfl_xor(v, (int)o);
+    if ((lane_id() & (width - 1)) == 0 && k < a.nch) atomicAdd(&sacc[c], v);
+    __syncthreads();
+    const uint64_t kt = (tile << (TL - a.M)) + tid;
+    if (tid < cpw && kt < a.nch) {
+      a.chunk_bits[kt] = sacc[tid] & 0xFFFFFu;
+      a.chunk_brk[kt] = sacc[tid] >> 20;
+    }
   }
   if (bad) raise_status(a.status, HF_ERR_SYMBOL);
-  atomicAdd(&sbits, bits);
-  atomicAdd(&sbrk, brk);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.chunk_bits[k] = sbits;
-    a.chunk_brk[k] = sbrk;
-  }
 }
 
 // offsets[k] = sum over j < k of ceil(bits_j / 32); brk_off likewise for the
-// breaking counts; totals at [nch].  One workgroup.
+// breaking counts; totals at [nch].  One workgroup, kScanPer consecutive
+// chunks a thread.  Loads and stores go through LDS so that both are
+// coalesced: a chunk's words and breaking groups (each at most 2^11) are
+// packed into one word, brk << 16 | words, and so are the in-thread
+// exclusive prefixes (at most 7 chunks, < 2^14 each).
 __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
+  constexpr uint32_t T = kScanThreads * kScanPer;  // chunks an iteration
+  __shared__ uint32_t pk[T];
+  __shared__ uint32_t base_w[kScanThreads], base_b[kScanThreads];
   __shared__ uint32_t wtot[kScanThreads / kWave];
   __shared__ uint64_t carry_w, carry_b;
-  if (threadIdx.x == 0) carry_w = carry_b = 0;
-  __syncthreads();
-  for (uint64_t base = 0; base < a.nch; base += kScanThreads) {
-    const uint64_t k = base + threadIdx.x;
-    const uint32_t w = k < a.nch ? (a.chunk_bits[k] + 31) / 32 : 0u;
-    const uint32_t b = k < a.nch ? a.chunk_brk[k] : 0u;
-    uint32_t tw, tb;
-    const uint32_t pw = block_exclusive_scan<kScanThreads / kWave>(w, wtot, &tw);
-    __syncthreads();
-    const uint32_t pb = block_exclusive_scan<kScanThreads / kWave>(b, wtot, &tb);
-    if (k < a.nch) {
-      a.offsets[k] = carry_w + pw;
-      a.brk_off[k] = carry_b + pb;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) carry_w = carry_b = 0;
+  for (uint64_t base = 0; base < a.nch; base += T) {
+#pragma unroll
+    for (uint32_t i = tid; i < T; i += kScanThreads) {
+      const uint64_t k = base + i;
+      pk[i] = k < a.nch ? (a.chunk_brk[k] << 16) | ((a.chunk_bits[k] + 31) / 32) : 0u;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    uint32_t v[kScanPer], sw = 0, sb = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      v[j] = pk[tid * kScanPer + j];
+      sw += v[j] & 0xFFFFu;
+      sb += v[j] >> 16;
+    }
+    uint32_t tw, tb;
+    const uint32_t pw = block_exclusive_scan<kScanThreads / kWave>(sw, wtot, &tw);
+    __syncthreads();
+    const uint32_t pb = block_exclusive_scan<kScanThreads / kWave>(sb, wtot, &tb);
+    base_w[tid] = pw;
+    base_b[tid] = pb;
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      pk[tid * kScanPer + j] = run;
+      run += v[j];
+    }
+    __syncthreads();
+    const uint64_t cw = carry_w, cb = carry_b;
+#pragma unroll
+    for (uint32_t i = tid; i < T; i += kScanThreads) {
+      const uint64_t k = base + i;
+      if (k < a.nch) {
+        const uint32_t o = i / kScanPer, p = pk[i];
+        a.offsets[k] = cw + base_w[o] + (p & 0xFFFFu);
+        a.brk_off[k] = cb + base_b[o] + (p >> 16);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
       carry_w += tw;
       carry_b += tb;
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  __syncthreads();
+  if (tid == 0) {
     a.offsets[a.nch] = carry_w;
     a.brk_off[a.nch] = carry_b;
     a.nbreak[0] = carry_b;
@@ -131,72 +270,101 @@ __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
   }
 }
 
-template <int SB>
-__global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a) {
-  __shared__ uint32_t img[1u << 12];  // the chunk's words, at most one per symbol
+// The workgroup's chunks are consecutive in the output, so their words form
+// one LDS image: a group's word has at most 32 bits (and two symbols at
+// least), so a tile holds at most 2^11 words plus one of padding a chunk.
+template <int SB, int R, bool TAB>
+__global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a, uint64_t ntiles) {
+  constexpr int PER = pf_per<R>();
+  constexpr uint32_t G = 1u << R, TL = pf_tile_log2<R>();
+  __shared__ uint32_t img[(1u << 11) + kPfMaxChunks];
   __shared__ uint32_t wtot[kPfWaves];
-  const uint64_t k = blockIdx.x;
-  const uint64_t lo = k << a.M;
-  const uint64_t hi = std::min<uint64_t>(a.n, lo + (1ull << a.M));
-  const uint32_t G = 1u << a.r;
-  const uint32_t ng = (uint32_t)((hi - lo + G - 1) >> a.r);
-  const uint64_t w0 = a.offsets[k];
-  const uint32_t nw = (uint32_t)(a.offsets[k + 1] - w0);
-  for (uint32_t i = threadIdx.x; i < nw; i += kPfThreads) img[i] = 0;
-  // contiguous groups per thread, so a workgroup scan gives every group's place
-  const uint32_t per = (ng + kPfThreads - 1) / kPfThreads;
-  const uint32_t ga = std::min(ng, threadIdx.x * per);
-  const uint32_t gb = std::min(ng, ga + per);
-  uint32_t word[kPfMaxPer], len[kPfMaxPer];
-  uint32_t bits = 0, brk = 0;
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < kPfMaxPer; ++j) {
-    len[j] = 0;
-    word[j] = 0;
-    const uint32_t g = ga + j;
-    if (g < gb) {
-      const uint64_t g0 = lo + ((uint64_t)g << a.r);
-      group_word<SB>(a.sym, g0, std::min<uint64_t>(hi, g0 + G), a.cl, a.cw, a.A, word[j], len[j], bad);
-      if (len[j] > 32) ++brk;
-      else bits += len[j];
-    }
-  }
-  uint32_t tot;
-  // bits of a chunk < 2^18, breaking groups < 2^12: one packed scan
-  const uint32_t pre = block_exclusive_scan<kPfWaves>((brk << 20) | bits, wtot, &tot);
-  uint32_t pos = pre & 0xFFFFFu;
-  uint64_t bpos = a.brk_off[k] + (pre >> 20);
-  const uint64_t gbase = lo >> a.r;
+  __shared__ uint32_t cstart[kPfMaxChunks];
+  const uint8_t* cl;
+  const uint32_t* cw;
+  pf_stage_book<TAB>(a, cl, cw);
+  const uint32_t tid = threadIdx.x;
   const bool fits = a.offsets[a.nch] <= a.cap_words;
+  bool bad = false;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t k0 = tile << (TL - a.M);
+    const uint64_t kend = std::min<uint64_t>(a.nch, k0 + (1u << (TL - a.M)));
+    const uint64_t w0 = a.offsets[k0];
+    const uint32_t nw = (uint32_t)(a.offsets[kend] - w0);
+    for (uint32_t i = tid; i < nw; i += kPfThreads) img[i] = 0;
+    uint32_t c, ga, gb;
+    uint64_t k, lo, hi;
+    pf_thread_groups<R>(a, tile, c, k, lo, hi, ga, gb);
+    uint32_t word[PER], len[PER], syms[PER << R];
+    thread_words<SB, R, PER, TAB>(a.sym, a.n, lo, hi, ga, gb, cl, cw, a.A, word, len, syms, bad);
+    uint32_t bits = 0, brk = 0;
 #pragma unroll
-  for (int j = 0; j < kPfMaxPer; ++j) {
-    const uint32_t g = ga + j;
-    if (g >= gb) break;
-    const uint32_t L = len[j];
-    if (L > 32) {
-      if (bpos < a.brk_cap) {
-        a.brk_groups[bpos] = gbase + g;
-        const uint64_t g0 = lo + ((uint64_t)g << a.r);
-        for (uint32_t i = 0; i < G; ++i) {
-          const uint32_t s = g0 + i < hi ? sym_at<SB>(a.sym, g0 + i) : 0u;
-          if (SB == 1) ((uint8_t*)a.brk_syms)[bpos * G + i] = (uint8_t)s;
-          else ((uint16_t*)a.brk_syms)[bpos * G + i] = (uint16_t)s;
-        }
-      }
-      ++bpos;
-      continue;
+    for (int j = 0; j < PER; ++j) {
+      brk += len[j] > 32;
+      bits += len[j] > 32 ? 0u : len[j];
     }
-    const uint32_t left = L == 32 ? word[j] : word[j] << (32 - L);
-    const uint32_t idx = pos >> 5, sh = pos & 31;
-    atomicOr(&img[idx], left >> sh);
-    if (sh + L > 32) atomicOr(&img[idx + 1], left << (32 - sh));
-    pos += L;
+    uint32_t tot;
+    // a tile's bits <= 2^16, breaking groups <= 2^11: one packed scan
+    const uint32_t pre = block_exclusive_scan<kPfWaves>((brk << 20) | bits, wtot, &tot);
+    if (k < a.nch && ga == 0) cstart[c] = pre;  // the thread holding the chunk's first group
+    __syncthreads();
+    uint32_t pos = 0;
+    if (k < a.nch) pos = (uint32_t)(a.offsets[k] - w0) * 32 + ((pre & 0xFFFFFu) - (cstart[c] & 0xFFFFFu));
+    uint64_t bpos = a.brk_off[k0] + (pre >> 20);
+    const uint64_t gbase = lo >> R;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t g = ga + j;
+      if (g >= gb) break;
+      const uint32_t L = len[j];
+      if (L > 32) {
+        if (bpos < a.brk_cap) {
+          a.brk_groups[bpos] = gbase + g;
+#pragma unroll
+          for (uint32_t i = 0; i < G; ++i) {  // the group's symbols, 0 past the stream's end
+            const uint32_t s = syms[j * G + i];
+            if (SB == 1) ((uint8_t*)a.brk_syms)[bpos * G + i] = (uint8_t)s;
+            else ((uint16_t*)a.brk_syms)[bpos * G + i] = (uint16_t)s;
+          }
+        }
+        ++bpos;
+        continue;
+      }
+      const uint32_t left = L == 32 ? word[j] : word[j] << (32 - L);
+      const uint32_t idx = pos >> 5, sh = pos & 31;
+      atomicOr(&img[idx], left >> sh);
+      if (sh + L > 32) atomicOr(&img[idx + 1], left << (32 - sh));
+      pos += L;
+    }
+    __syncthreads();
+    if (fits)
+      for (uint32_t i = tid; i < nw; i += kPfThreads) a.out[w0 + i] = img[i];
+    __syncthreads();  // the image and cstart are rewritten by the next tile
   }
   if (bad) raise_status(a.status, HF_ERR_SYMBOL);
-  __syncthreads();
-  if (fits)
-    for (uint32_t i = threadIdx.x; i < nw; i += kPfThreads) a.out[w0 + i] = img[i];
+}
+
+template <int SB, int R>
+void launch_pf_r(bool write, const PfArgs& a, uint64_t ntiles, uint32_t nblk, hipStream_t stream) {
+  if (a.A <= kPfTabAlphabet) {
+    const uint32_t lds = pf_tab_bytes(a.A);
+    if (write) pf_write_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a, ntiles);
+    else pf_count_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a, ntiles);
+  } else {
+    if (write) pf_write_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a, ntiles);
+    else pf_count_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a, ntiles);
+  }
+}
+
+template <int SB>
+void launch_pf(bool write, const PfArgs& a, uint32_t r, uint64_t ntiles, uint32_t nblk, hipStream_t stream) {
+  switch (r) {
+    case 1: launch_pf_r<SB, 1>(write, a, ntiles, nblk, stream); break;
+    case 2: launch_pf_r<SB, 2>(write, a, ntiles, nblk, stream); break;
+    case 3: launch_pf_r<SB, 3>(write, a, ntiles, nblk, stream); break;
+    case 4: launch_pf_r<SB, 4>(write, a, ntiles, nblk, stream); break;
+    default: launch_pf_r<SB, 5>(write, a, ntiles, nblk, stream); break;
+  }
 }
 
 }  // namespace
@@ -209,7 +377,7 @@ size_t paper_workspace_bytes(uint64_t n, uint32_t chunk_log2) {
 hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
                                uint32_t M, uint32_t r, uint32_t* out, uint64_t cap_words, uint64_t* offsets,
                                uint64_t* brk_groups, void* brk_syms, uint64_t brk_cap, uint64_t* nbreak, void* ws,
-                               uint32_t* status, hipStream_t stream, const KernelTimer& timer) {
+                               uint32_t* status, uint32_t cus, hipStream_t stream, const KernelTimer& timer) {
   const uint64_t nch = (n + (1ull << M) - 1) >> M;
   if (n == 0) {
     hipError_t e = launch_fill_u64(offsets, 1, 0, stream);
@@ -220,10 +388,9 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
   a.sym = sym;
   a.n = n;
   a.cl = book.cl;
-  a.cw = book.cw;
+  a.cw32 = (const uint32_t*)book.cw;
   a.A = book.alphabet;
   a.M = M;
-  a.r = r;
   a.nch = nch;
   a.chunk_bits = (uint32_t*)ws;
   a.chunk_brk = a.chunk_bits + nch;
@@ -236,16 +403,20 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
   a.brk_cap = brk_cap;
   a.nbreak = nbreak;
   a.status = status;
+  const uint32_t cl2 = (r < 5 ? 12u : 13u) - M;  // chunks per tile, log2 (pf_tile_log2)
+  const uint64_t ntiles = (nch + (1u << cl2) - 1) >> cl2;
+  // workgroups loop over tiles: as many as fit on the chip at once
+  const uint32_t nblk = (uint32_t)std::min<uint64_t>(ntiles, (uint64_t)cus * kPfBlocksPerCu);
   timer.before(stream);
-  if (sym_bytes == 1) pf_count_kernel<1><<<(uint32_t)nch, kPfThreads, 0, stream>>>(a);
-  else pf_count_kernel<2><<<(uint32_t)nch, kPfThreads, 0, stream>>>(a);
+  if (sym_bytes == 1) launch_pf<1>(false, a, r, ntiles, nblk, stream);
+  else launch_pf<2>(false, a, r, ntiles, nblk, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   pf_scan_kernel<<<1, kScanThreads, 0, stream>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (sym_bytes == 1) pf_write_kernel<1><<<(uint32_t)nch, kPfThreads, 0, stream>>>(a);
-  else pf_write_kernel<2><<<(uint32_t)nch, kPfThreads, 0, stream>>>(a);
+  if (sym_bytes == 1) launch_pf<1>(true, a, r, ntiles, nblk, stream);
+  else launch_pf<2>(true, a, r, ntiles, nblk, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   timer.after(stream);
