@@ -110,7 +110,11 @@ struct PfArgs {
   uint64_t nch;
   uint32_t* chunk_bits;  // ws
   uint32_t* chunk_brk;   // ws
-  uint64_t* brk_off;     // ws: [nch + 1]
+  uint32_t* tile_w;      // ws: per tile, its chunks' words
+  uint32_t* tile_b;      // ws: per tile, its breaking groups
+  uint64_t* tile_off_w;  // ws: [ntiles + 1], exclusive scan of tile_w
+  uint64_t* tile_off_b;  // ws: [ntiles + 1], exclusive scan of tile_b
+  uint64_t ntiles;
   uint64_t* offsets;     // out: chunk word offsets [nch + 1]
   uint32_t* out;
   uint64_t cap_words;
@@ -165,7 +169,8 @@ __device__ __forceinline__ void pf_stage_book(const PfArgs& a, const uint8_t*& c
 
 // Each workgroup stages the book once and loops over tiles.
 template <int SB, int R, bool TAB>
-__global__ __launch_bounds__(kPfThreads) void pf_count_kernel(PfArgs a, uint64_t ntiles) {
+__global__ __launch_bounds__(kPfThreads) void pf_count_kernel(PfArgs a) {
+  const uint64_t ntiles = a.ntiles;
   constexpr uint32_t TL = pf_tile_log2<R>();
   constexpr int PER = pf_per<R>();
   __shared__ uint32_t sacc[kPfMaxChunks];  // per chunk: breaking groups << 20 | bits
@@ -192,24 +197,40 @@ __global__ __launch_bounds__(kPfThreads) void pf_count_kernel(PfArgs a, uint64_t
     // the lanes of the chunk (a power of two up to the whole wave)
     uint32_t v = (brk << 20) | bits;
     const uint32_t width = std::min(1u << (a.M + 8 - TL), (uint32_t)kWave);
-    for (uint32_t o = 1; o < width; o <<= 1) v += __shfl_xor(v, (int)o);
-    if ((lane_id() & (width - 1)) == 0 && k < a.nch) atomicAdd(&sacc[c], v);
+    if (width == kWave) {  // the wave lies in one chunk: DPP sum, total in the last lane
+      v = wave_inclusive_scan(v);
+      if (lane_id() == kWave - 1 && k < a.nch) atomicAdd(&sacc[c], v);
+    } else {
+      for (uint32_t o = 1; o < width; o <<= 1) v += __shfl_xor(v, (int)o);
+      if ((lane_id() & (width - 1)) == 0 && k < a.nch) atomicAdd(&sacc[c], v);
+    }
     __syncthreads();
     const uint64_t kt = (tile << (TL - a.M)) + tid;
-    if (tid < cpw && kt < a.nch) {
-      a.chunk_bits[kt] = sacc[tid] & 0xFFFFFu;
-      a.chunk_brk[kt] = sacc[tid] >> 20;
+    if (tid < kWave) {  // wave 0: the chunks' counts and the tile's totals
+      const uint32_t sv = tid < cpw && kt < a.nch ? sacc[tid] : 0u;
+      if (tid < cpw && kt < a.nch) {
+        a.chunk_bits[kt] = sv & 0xFFFFFu;
+        a.chunk_brk[kt] = sv >> 20;
+      }
+      // a tile's words <= 2^11 + 32 and breaking groups <= 2^11: one packed DPP sum
+      const uint32_t t = wave_inclusive_scan((sv >> 20) << 16 | (((sv & 0xFFFFFu) + 31) / 32));
+      if (tid == kWave - 1) {
+        a.tile_w[tile] = t & 0xFFFFu;
+        a.tile_b[tile] = t >> 16;
+      }
     }
   }
   if (bad) raise_status(a.status, HF_ERR_SYMBOL);
 }
 
-// offsets[k] = sum over j < k of ceil(bits_j / 32); brk_off likewise for the
-// breaking counts; totals at [nch].  One workgroup, kScanPer consecutive
-// chunks a thread.  Loads and stores go through LDS so that both are
-// coalesced: a chunk's words and breaking groups (each at most 2^11) are
-// packed into one word, brk << 16 | words, and so are the in-thread
-// exclusive prefixes (at most 7 chunks, < 2^14 each).
+// tile_off_w[t] = sum over tiles j < t of their words (each chunk's
+// ceil(bits / 32)), tile_off_b likewise for the breaking groups; totals at
+// [ntiles], and the stream's total words also at offsets[nch].  One
+// workgroup, kScanPer consecutive tiles a thread.  Loads and stores go
+// through LDS so that both are coalesced: a tile's words (at most 2^11 plus
+// one a chunk) and breaking groups (at most 2^11) are packed into one word,
+// brk << 16 | words, and so are the in-thread exclusive prefixes (at most 7
+// tiles, < 2^16 each).
 __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
   constexpr uint32_t T = kScanThreads * kScanPer;  // chunks an iteration
   __shared__ uint32_t pk[T];
@@ -218,11 +239,11 @@ __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
   __shared__ uint64_t carry_w, carry_b;
   const uint32_t tid = threadIdx.x;
   if (tid == 0) carry_w = carry_b = 0;
-  for (uint64_t base = 0; base < a.nch; base += T) {
+  for (uint64_t base = 0; base < a.ntiles; base += T) {
 #pragma unroll
     for (uint32_t i = tid; i < T; i += kScanThreads) {
       const uint64_t k = base + i;
-      pk[i] = k < a.nch ? (a.chunk_brk[k] << 16) | ((a.chunk_bits[k] + 31) / 32) : 0u;
+      pk[i] = k < a.ntiles ? (a.tile_b[k] << 16) | a.tile_w[k] : 0u;
     }
     __syncthreads();
     uint32_t v[kScanPer], sw = 0, sb = 0;
@@ -249,10 +270,10 @@ __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
 #pragma unroll
     for (uint32_t i = tid; i < T; i += kScanThreads) {
       const uint64_t k = base + i;
-      if (k < a.nch) {
+      if (k < a.ntiles) {
         const uint32_t o = i / kScanPer, p = pk[i];
-        a.offsets[k] = cw + base_w[o] + (p & 0xFFFFu);
-        a.brk_off[k] = cb + base_b[o] + (p >> 16);
+        a.tile_off_w[k] = cw + base_w[o] + (p & 0xFFFFu);
+        a.tile_off_b[k] = cb + base_b[o] + (p >> 16);
       }
     }
     __syncthreads();
@@ -264,7 +285,8 @@ __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
   __syncthreads();
   if (tid == 0) {
     a.offsets[a.nch] = carry_w;
-    a.brk_off[a.nch] = carry_b;
+    a.tile_off_w[a.ntiles] = carry_w;
+    a.tile_off_b[a.ntiles] = carry_b;
     a.nbreak[0] = carry_b;
     if (carry_w > a.cap_words || carry_b > a.brk_cap) raise_status(a.status, HF_ERR_CAPACITY);
   }
@@ -274,12 +296,14 @@ __global__ __launch_bounds__(kScanThreads) void pf_scan_kernel(PfArgs a) {
 // one LDS image: a group's word has at most 32 bits (and two symbols at
 // least), so a tile holds at most 2^11 words plus one of padding a chunk.
 template <int SB, int R, bool TAB>
-__global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a, uint64_t ntiles) {
+__global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a) {
+  const uint64_t ntiles = a.ntiles;
   constexpr int PER = pf_per<R>();
   constexpr uint32_t G = 1u << R, TL = pf_tile_log2<R>();
   __shared__ uint32_t img[(1u << 11) + kPfMaxChunks];
   __shared__ uint32_t wtot[kPfWaves];
   __shared__ uint32_t cstart[kPfMaxChunks];
+  __shared__ uint32_t coff[kPfMaxChunks];  // each chunk's first word in the tile
   const uint8_t* cl;
   const uint32_t* cw;
   pf_stage_book<TAB>(a, cl, cw);
@@ -288,10 +312,19 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a, uint64_t
   bool bad = false;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t k0 = tile << (TL - a.M);
-    const uint64_t kend = std::min<uint64_t>(a.nch, k0 + (1u << (TL - a.M)));
-    const uint64_t w0 = a.offsets[k0];
-    const uint32_t nw = (uint32_t)(a.offsets[kend] - w0);
+    const uint64_t w0 = a.tile_off_w[tile];
+    const uint32_t nw = (uint32_t)(a.tile_off_w[tile + 1] - w0);
     for (uint32_t i = tid; i < nw; i += kPfThreads) img[i] = 0;
+    if (tid < kWave) {  // wave 0: the chunks' word offsets, in the tile and in the stream
+      const uint64_t kk = k0 + tid;
+      const bool own = tid < (1u << (TL - a.M)) && kk < a.nch;
+      const uint32_t w = own ? (a.chunk_bits[kk] + 31) / 32 : 0u;
+      const uint32_t x = wave_inclusive_scan(w) - w;
+      if (own) {
+        coff[tid] = x;
+        a.offsets[kk] = w0 + x;
+      }
+    }
     uint32_t c, ga, gb;
     uint64_t k, lo, hi;
     pf_thread_groups<R>(a, tile, c, k, lo, hi, ga, gb);
@@ -309,8 +342,8 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a, uint64_t
     if (k < a.nch && ga == 0) cstart[c] = pre;  // the thread holding the chunk's first group
     __syncthreads();
     uint32_t pos = 0;
-    if (k < a.nch) pos = (uint32_t)(a.offsets[k] - w0) * 32 + ((pre & 0xFFFFFu) - (cstart[c] & 0xFFFFFu));
-    uint64_t bpos = a.brk_off[k0] + (pre >> 20);
+    if (k < a.nch) pos = coff[c] * 32 + ((pre & 0xFFFFFu) - (cstart[c] & 0xFFFFFu));
+    uint64_t bpos = a.tile_off_b[tile] + (pre >> 20);
     const uint64_t gbase = lo >> R;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
@@ -339,39 +372,41 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a, uint64_t
     __syncthreads();
     if (fits)
       for (uint32_t i = tid; i < nw; i += kPfThreads) a.out[w0 + i] = img[i];
-    __syncthreads();  // the image and cstart are rewritten by the next tile
+    __syncthreads();  // the image, cstart and coff are rewritten by the next tile
   }
   if (bad) raise_status(a.status, HF_ERR_SYMBOL);
 }
 
 template <int SB, int R>
-void launch_pf_r(bool write, const PfArgs& a, uint64_t ntiles, uint32_t nblk, hipStream_t stream) {
+void launch_pf_r(bool write, const PfArgs& a, uint32_t nblk, hipStream_t stream) {
   if (a.A <= kPfTabAlphabet) {
     const uint32_t lds = pf_tab_bytes(a.A);
-    if (write) pf_write_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a, ntiles);
-    else pf_count_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a, ntiles);
+    if (write) pf_write_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a);
+    else pf_count_kernel<SB, R, true><<<nblk, kPfThreads, lds, stream>>>(a);
   } else {
-    if (write) pf_write_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a, ntiles);
-    else pf_count_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a, ntiles);
+    if (write) pf_write_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a);
+    else pf_count_kernel<SB, R, false><<<nblk, kPfThreads, 0, stream>>>(a);
   }
 }
 
 template <int SB>
-void launch_pf(bool write, const PfArgs& a, uint32_t r, uint64_t ntiles, uint32_t nblk, hipStream_t stream) {
+void launch_pf(bool write, const PfArgs& a, uint32_t r, uint32_t nblk, hipStream_t stream) {
   switch (r) {
-    case 1: launch_pf_r<SB, 1>(write, a, ntiles, nblk, stream); break;
-    case 2: launch_pf_r<SB, 2>(write, a, ntiles, nblk, stream); break;
-    case 3: launch_pf_r<SB, 3>(write, a, ntiles, nblk, stream); break;
-    case 4: launch_pf_r<SB, 4>(write, a, ntiles, nblk, stream); break;
-    default: launch_pf_r<SB, 5>(write, a, ntiles, nblk, stream); break;
+    case 1: launch_pf_r<SB, 1>(write, a, nblk, stream); break;
+    case 2: launch_pf_r<SB, 2>(write, a, nblk, stream); break;
+    case 3: launch_pf_r<SB, 3>(write, a, nblk, stream); break;
+    case 4: launch_pf_r<SB, 4>(write, a, nblk, stream); break;
+    default: launch_pf_r<SB, 5>(write, a, nblk, stream); break;
   }
 }
 
 }  // namespace
 
+// Chunk counts (bits, breaking groups), tile totals, and the tiles' two
+// exclusive scans; a tile holds at least one chunk, so nch bounds the tiles.
 size_t paper_workspace_bytes(uint64_t n, uint32_t chunk_log2) {
   const uint64_t nch = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
-  return (size_t)(nch * 8 + 255) / 256 * 256 + (size_t)((nch + 1) * 8 + 255) / 256 * 256;
+  return 2 * ((size_t)(nch * 8 + 255) / 256 * 256) + 2 * ((size_t)((nch + 1) * 8 + 255) / 256 * 256);
 }
 
 hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, const hf_codebook& book,
@@ -394,7 +429,11 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
   a.nch = nch;
   a.chunk_bits = (uint32_t*)ws;
   a.chunk_brk = a.chunk_bits + nch;
-  a.brk_off = (uint64_t*)((char*)ws + (nch * 8 + 255) / 256 * 256);
+  const size_t pair_bytes = (size_t)(nch * 8 + 255) / 256 * 256, scan_bytes = (size_t)((nch + 1) * 8 + 255) / 256 * 256;
+  a.tile_w = (uint32_t*)((char*)ws + pair_bytes);
+  a.tile_b = a.tile_w + nch;
+  a.tile_off_w = (uint64_t*)((char*)ws + 2 * pair_bytes);
+  a.tile_off_b = (uint64_t*)((char*)ws + 2 * pair_bytes + scan_bytes);
   a.offsets = offsets;
   a.out = out;
   a.cap_words = cap_words;
@@ -405,18 +444,19 @@ hipError_t launch_encode_paper(const void* sym, uint64_t n, uint32_t sym_bytes, 
   a.status = status;
   const uint32_t cl2 = (r < 5 ? 12u : 13u) - M;  // chunks per tile, log2 (pf_tile_log2)
   const uint64_t ntiles = (nch + (1u << cl2) - 1) >> cl2;
+  a.ntiles = ntiles;
   // workgroups loop over tiles: as many as fit on the chip at once
   const uint32_t nblk = (uint32_t)std::min<uint64_t>(ntiles, (uint64_t)cus * kPfBlocksPerCu);
   timer.before(stream);
-  if (sym_bytes == 1) launch_pf<1>(false, a, r, ntiles, nblk, stream);
-  else launch_pf<2>(false, a, r, ntiles, nblk, stream);
+  if (sym_bytes == 1) launch_pf<1>(false, a, r, nblk, stream);
+  else launch_pf<2>(false, a, r, nblk, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   pf_scan_kernel<<<1, kScanThreads, 0, stream>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (sym_bytes == 1) launch_pf<1>(true, a, r, ntiles, nblk, stream);
-  else launch_pf<2>(true, a, r, ntiles, nblk, stream);
+  if (sym_bytes == 1) launch_pf<1>(true, a, r, nblk, stream);
+  else launch_pf<2>(true, a, r, nblk, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   timer.after(stream);
