@@ -43,8 +43,8 @@ def run(x, ref, M, r, **kw):
     return code, out, offs, bg, bs, nb
 
 
-def check(x, M, r):
-    ref = oracle.codebook(oracle.histogram(x, 1024 if x.dtype == np.uint16 else 256))
+def check(x, M, r, alphabet=None):
+    ref = oracle.codebook(oracle.histogram(x, alphabet or (1024 if x.dtype == np.uint16 else 256)))
     code, out, offs, bg, bs, nb = run(x, ref, M, r)
     assert code == 0
     w, o, b, s = pf.encode(x, ref.cl, ref.cw, M, r)
@@ -71,6 +71,16 @@ def test_matches_oracle(M, r, sigma):
 def test_bytes():
     x = W.zipf_bytes(n=1_000_001, seed=3)
     check(x, 10, 3)
+
+
+@pytest.mark.parametrize("M,r", [(10, 1), (12, 2)])
+def test_large_alphabet(M, r):
+    """An alphabet above the LDS copy's 4096 symbols: the book is read from
+    global memory (wide Gaussian codes: some 6600 used symbols up to 9483,
+    8.3 bits a symbol on average, so that groups both fit and break)."""
+    x = W.gaussian_codes(n=300_007, alphabet=16384, sigma=2000.0, seed=4)
+    nbreak = check(x, M, r, 16384)
+    assert 0 < nbreak < (x.size >> r)
 
 
 def test_capacity_errors_write_nothing_past_capacity():
@@ -132,3 +142,47 @@ def test_full_size_lorenzo_sampled_chunks():
         g0 = (k * C) >> r
         mine = groups[(groups >= g0) & (groups < g0 + (C >> r))] - g0
         assert np.array_equal(mine, b)
+
+
+@pytest.fixture(scope="module")
+def long_stream():
+    """20 M Lorenzo codes (a ragged length) with a wide Gaussian segment
+    spliced into the middle, and the oracle's book for them."""
+    n = 20_000_003
+    x = W.make("lorenzo3d_512cube_u16_A1024")[:n].copy()
+    wide = W.gaussian_codes(n=1 << 20, alphabet=1024, sigma=40.0, seed=9)
+    x[n // 2:n // 2 + wide.size] = wide
+    return x, oracle.codebook(oracle.histogram(x, 1024))
+
+
+@pytest.mark.parametrize("M,r", [(8, 1), (10, 2), (11, 3), (12, 4), (9, 5)])
+def test_long_ragged_stream_sampled_chunks(long_stream, M, r):
+    """A stream long enough that every workgroup encodes many tiles in turn:
+    sampled chunks (the first, the last, two in the wide segment, random
+    ones) against the oracle: words, chunk offsets, breaking groups and
+    their symbols."""
+    x, ref = long_stream
+    n = x.size
+    code, out, offs, bg, bs, nb = run(x, ref, M, r)
+    assert code == 0
+    C, G = 1 << M, 1 << r
+    o = offs.cpu().numpy().view(np.uint64)
+    nch = (n + C - 1) // C
+    assert o.size == nch + 1 and np.all(np.diff(o.astype(np.int64)) >= 0)
+    k_all = int(nb.item())
+    groups = bg[:k_all].cpu().numpy().view(np.uint64)
+    syms = bs[: k_all << r].cpu().numpy().view(np.uint16).reshape(k_all, G)
+    assert np.all(np.diff(groups.astype(np.int64)) > 0)
+    rng = np.random.default_rng(M * 10 + r)
+    mid = (n // 2 + (1 << 19)) // C  # inside the wide segment
+    for k in list(rng.integers(0, nch, 24)) + [0, mid, mid + 1, nch - 1]:
+        xs = x[k * C:(k + 1) * C]
+        w, oo, b, s = pf.encode(xs, ref.cl, ref.cw, M, r)
+        assert int(o[k + 1] - o[k]) == int(oo[-1])
+        assert np.array_equal(out[int(o[k]):int(o[k + 1])].cpu().numpy().view(np.uint32), w)
+        g0 = (k * C) >> r
+        sel = (groups >= g0) & (groups < g0 + ((xs.size + G - 1) >> r))
+        assert np.array_equal(groups[sel] - g0, b)
+        assert np.array_equal(syms[sel].reshape(-1), s.reshape(-1))
+        if k == mid and r >= 2:
+            assert b.size > 0  # the side channel is exercised inside the long stream
