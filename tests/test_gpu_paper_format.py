@@ -83,6 +83,33 @@ def test_large_alphabet(M, r):
     assert 0 < nbreak < (x.size >> r)
 
 
+@pytest.mark.parametrize("M,r", [(10, 1), (12, 1), (10, 2)])
+def test_long_codes_with_lds_book(M, r):
+    """Codes of up to 27 bits in an alphabet the workgroups copy to LDS,
+    merged into words that they nearly fill.  The book is the oracle's for
+    Fibonacci counts on 45 symbols and 1 on the rest (lengths 2..27); the
+    stream draws the 45 symbols uniformly, so at r = 1 about 1800 groups
+    fit with a code over 25 bits."""
+    A = 1024
+    h = np.ones(A, np.uint64)
+    f = [1, 2]
+    while len(f) < 45:
+        f.append(f[-1] + f[-2])
+    h[:45] = f[::-1]
+    ref = oracle.codebook(h)
+    assert ref.cl.max() > 25
+    x = np.random.default_rng(1).integers(0, 45, 200_003).astype(np.uint16)
+    code, out, offs, bg, bs, nb = run(x, ref, M, r)
+    assert code == 0
+    w, o, b, s = pf.encode(x, ref.cl, ref.cw, M, r)
+    assert np.array_equal(offs.cpu().numpy().view(np.uint64), o)
+    assert np.array_equal(out[: int(o[-1])].cpu().numpy().view(np.uint32), w)
+    k = int(nb.item())
+    assert k == b.size
+    assert np.array_equal(bg[:k].cpu().numpy().view(np.uint64), b)
+    assert np.array_equal(bs[: k << r].cpu().numpy().view(np.uint16), s)
+
+
 def test_capacity_errors_write_nothing_past_capacity():
     x = W.gaussian_codes(n=50_000, alphabet=1024, sigma=40.0, seed=1)
     ref = oracle.codebook(oracle.histogram(x, 1024))
