@@ -50,6 +50,9 @@ def parse():
                         "then codebook and encode; "
                         "paperformat: the paper's ReduceShuffleMerge<M,r> format, swept over M x r (Table 3's shape); "
                         "codebook: hf_build_codebook time against alphabet size (Table 2's shape)")
+    p.add_argument("--jsonl", default="",
+                   help="pipeline mode: also append one record of the run to this file (JSON Lines): the printed "
+                        "line plus the input's sha256, the generator seed, the device and the host's cores")
     p.add_argument("--graph", action="store_true",
                    help="pipeline mode: time replays of the whole pass captured as one HIP graph (small "
                         "streams are bound by per-launch host overhead); stage times then come from eager steps")
@@ -1090,6 +1093,31 @@ def main():
         "cpu_parallel": cpu_par,
     }
     print(json.dumps(line), flush=True)
+    if args.jsonl:
+        append_run_record(args.jsonl, line, x, torch.cuda.get_device_name(0))
+
+
+def append_run_record(path, line, x, device):
+    """One JSON Lines record per run: the bench line (config, n, alphabet,
+    average code length, longest code, per-stage us, GB/s, fraction of peak,
+    counter bytes, oracle times and their cores) plus what identifies the
+    input and the machine."""
+    import hashlib
+    import platform
+
+    rec = {
+        "time_utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()),
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(x).view(np.uint8)).hexdigest(),
+        "input_dtype": str(x.dtype),
+        "generator_seed": 0,  # every pipeline workload is drawn with seed 0 (workloads.make)
+        "device": device,
+        "host": platform.node(),
+        "host_cores": os.cpu_count(),
+        "argv": sys.argv[1:],
+        "line": line,
+    }
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
 
 
 if __name__ == "__main__":
