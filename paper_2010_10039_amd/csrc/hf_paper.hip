@@ -302,8 +302,8 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a) {
   constexpr uint32_t G = 1u << R, TL = pf_tile_log2<R>();
   __shared__ uint32_t img[(1u << 11) + kPfMaxChunks];
   __shared__ uint32_t wtot[kPfWaves];
-  __shared__ uint32_t cstart[kPfMaxChunks];
-  __shared__ uint32_t coff[kPfMaxChunks];  // each chunk's first word in the tile
+  __shared__ uint32_t cstart[kPfMaxChunks];  // each chunk's first bit in the tile's packed scan
+  __shared__ uint32_t coff[kPfMaxChunks];    // each chunk's first word in the tile
   const uint8_t* cl;
   const uint32_t* cw;
   pf_stage_book<TAB>(a, cl, cw);
@@ -315,13 +315,16 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a) {
     const uint64_t w0 = a.tile_off_w[tile];
     const uint32_t nw = (uint32_t)(a.tile_off_w[tile + 1] - w0);
     for (uint32_t i = tid; i < nw; i += kPfThreads) img[i] = 0;
-    if (tid < kWave) {  // wave 0: the chunks' word offsets, in the tile and in the stream
+    if (tid < kWave) {  // wave 0: the chunks' word offsets (in the tile and in the stream) and first bits
       const uint64_t kk = k0 + tid;
       const bool own = tid < (1u << (TL - a.M)) && kk < a.nch;
-      const uint32_t w = own ? (a.chunk_bits[kk] + 31) / 32 : 0u;
+      const uint32_t b = own ? a.chunk_bits[kk] : 0u;
+      const uint32_t w = (b + 31) / 32;
       const uint32_t x = wave_inclusive_scan(w) - w;
+      const uint32_t y = wave_inclusive_scan(b) - b;  // a tile's bits <= 2^16
       if (own) {
         coff[tid] = x;
+        cstart[tid] = y;
         a.offsets[kk] = w0 + x;
       }
     }
@@ -338,11 +341,10 @@ __global__ __launch_bounds__(kPfThreads) void pf_write_kernel(PfArgs a) {
     }
     uint32_t tot;
     // a tile's bits <= 2^16, breaking groups <= 2^11: one packed scan
+    // (its barrier also publishes wave 0's coff and cstart, and the cleared image)
     const uint32_t pre = block_exclusive_scan<kPfWaves>((brk << 20) | bits, wtot, &tot);
-    if (k < a.nch && ga == 0) cstart[c] = pre;  // the thread holding the chunk's first group
-    __syncthreads();
-    uint32_t pos = 0;
-    if (k < a.nch) pos = coff[c] * 32 + ((pre & 0xFFFFFu) - (cstart[c] & 0xFFFFFu));
+    uint32_t pos = 0;  // the chunk's bits before this thread's: the tile's, less the earlier chunks'
+    if (k < a.nch) pos = coff[c] * 32 + ((pre & 0xFFFFFu) - cstart[c]);
     uint64_t bpos = a.tile_off_b[tile] + (pre >> 20);
     const uint64_t gbase = lo >> R;
 #pragma unroll
